@@ -1,0 +1,63 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each mutant plants one bug in a copy of the oracle source (on the CPU), builds
+it, and runs the pin suite against it in a subprocess; the suite must fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lesasm_oracle.c")
+PINS = ["tests/test_oracle_refelem.py", "tests/test_oracle_vreman.py", "tests/test_oracle_exact.py",
+        "tests/test_oracle_invariants.py"]
+
+MUTANTS = {
+    "gradient_uses_J_inverse_untransposed": ("s += K[j][i] * dN[3 * a + j];", "s += K[i][j] * dN[3 * a + j];"),
+    "jacobian_transposed": ("s += x[3 * a + i] * dN[3 * a + j];", "s += x[3 * a + j] * dN[3 * a + i];"),
+    "emac_drops_divergence_term": ("C[i] = s + divu * ug[i];", "C[i] = s;"),
+    "strain_not_symmetrised": ("S[i][j] = G[i][j] + G[j][i];", "S[i][j] = 2.0 * G[i][j];"),
+    "pressure_gradient_sign": ("if (terms & TERM_PRES) f += dp[i];", "if (terms & TERM_PRES) f -= dp[i];"),
+    "residual_sign": ("R[3 * a + i] -= dV * (N[a] * f + s);", "R[3 * a + i] -= dV * (N[a] * f - s);"),
+    "pyramid_weights_swapped": ("const double W[2] = {1.0 / 6.0 + sqrt(10.0) / 48.0, 1.0 / 6.0 - sqrt(10.0) / 48.0};",
+                                "const double W[2] = {1.0 / 6.0 - sqrt(10.0) / 48.0, 1.0 / 6.0 + sqrt(10.0) / 48.0};"),
+    "tet_rule_point": ("const double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0", "const double a = (5.0 + 3.0 * sqrt(5.0)) / 21.0"),
+    "vreman_drops_minor": ("+ beta[1][1] * beta[2][2] - beta[1][2] * beta[1][2];", "+ beta[1][1] * beta[2][2];"),
+    "filter_width_sqrt": ("const double delta = cbrt(vol);", "const double delta = sqrt(vol);"),
+    "hex_zeta_derivative": ("dN[3 * a + 2] = 0.125 * za[a] * fx * fy;", "dN[3 * a + 2] = 0.125 * za[a] * fx * fz;"),
+    "prism_zeta_derivative": ("dN[3 * a + 2] = L[i] * dZ[j];", "dN[3 * a + 2] = L[i] * Z[j];"),
+    "pyramid_zeta_derivative": ("dN[3 * a + 2] = (-(A + B) * q + A * B) / (4.0 * q * q);",
+                                "dN[3 * a + 2] = (-(A + B) * q - A * B) / (4.0 * q * q);"),
+    "scatter_wrong_node": ("rhs[3 * fid[a] + i] += R[3 * a + i];", "rhs[3 * fid[(a + 1) % n] + i] += R[3 * a + i];"),
+    "lumped_mass_ignores_jacobian": ("M[fid[a]] += w[q] * d * N[a];", "M[fid[a]] += w[q] * N[a];"),
+    "viscosity_ignores_eddy": ("if (terms & TERM_SGS) visc += nut;", "if (terms & TERM_SGS) visc += 0.5 * nut;"),
+}
+
+
+def _run_pins(src_text, tmp_path):
+    sys.path.insert(0, ROOT)
+    from oracle.oracle import build
+    mut = tmp_path / "variant.c"
+    mut.write_text(src_text)
+    lib = build(str(mut), str(tmp_path / "libvariant.so"))
+    env = dict(os.environ, LESASM_ORACLE_LIB=lib)
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.slow
+def test_unmodified_copy_passes(tmp_path):
+    r = _run_pins(open(SRC).read(), tmp_path)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    r = _run_pins(src.replace(old, new), tmp_path)
+    assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
