@@ -1,0 +1,200 @@
+/*
+ * lesasm — explicit LES momentum-residual assembly on AMD Instinct MI355X.
+ *
+ * C ABI of the GPU library.  Every call returns an int status (LESASM_OK = 0,
+ * negative on error), never throws and never aborts; lesasm_last_error()
+ * gives the calling thread's last message.  Device pointers are plain
+ * pointers from hipMalloc (or a PyTorch tensor's data_ptr()) on the device
+ * that was current when the mesh was created; `stream` is a hipStream_t
+ * (NULL = the legacy default stream).  All device work is asynchronous on
+ * that stream and no call below synchronises the host unless it says so.
+ *
+ * What is computed follows Borrell et al., "Heterogeneous CPU/GPU
+ * co-execution of CFD simulations on the POWER9 architecture" (FGCS 2020):
+ *   - Section 3.2, equation (momentum): the filtered incompressible momentum
+ *     equation with rho = 1, kinematic viscosity nu, the EMAC convective form
+ *     C(u) = 2 eps(u) u + (div u) u with -|u|^2/2 folded into the modified
+ *     pressure p, the viscous term div[2 nu eps(u)] and the subgrid term
+ *     div(tau), tau = -2 nu_t eps(u), nu_t from Vreman's model.
+ *   - Section 3.2 and Algorithm 1 (step "Element assembly"): Galerkin
+ *     finite elements on linear hybrid meshes, assembled element by element.
+ *   - Section 3.4.3 (gather, computation, scatter; elements grouped by type
+ *     and integration rule into categories).
+ * The residual of local node a of element e, component i, is
+ *   R_ai = - sum_g w_g detJ_g [ N_a (C_i + dp/dx_i) + dN_a/dx_j 2 (nu + nu_t) eps_ij ]
+ * and rhs[node] = sum over the elements touching it, so that M_L du/dt = rhs.
+ *
+ * Element types, reference nodes (node order of the connectivity) and rules:
+ *   LESASM_TET04  (0,0,0) (1,0,0) (0,1,0) (0,0,1); 4-point degree-2 rule.
+ *   LESASM_PYR05  (-1,-1,0) (1,-1,0) (1,1,0) (-1,1,0) (0,0,1); rational basis,
+ *                 8-point conical product rule (Gauss-Legendre x Gauss-Jacobi).
+ *   LESASM_PEN06  (0,0,-1) (1,0,-1) (0,1,-1) (0,0,1) (1,0,1) (0,1,1); 3 x 2 rule.
+ *   LESASM_HEX08  (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) then zeta=+1; 2x2x2 Gauss.
+ * Filter width Delta_e = (element volume)^(1/3); lumped mass = row sums of
+ * the consistent mass matrix (the mass-matrix listing of Section 3.4.3).
+ */
+#ifndef LESASM_H
+#define LESASM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LESASM_VERSION 1
+
+/* ---- status codes ------------------------------------------------------ */
+#define LESASM_OK 0
+#define LESASM_E_INVALID_ARG -1      /* null/misaligned pointer, bad size, type or index */
+#define LESASM_E_INVERTED_ELEMENT -2 /* det J <= 0 at a Gauss point (user element id in message) */
+#define LESASM_E_OOM -3              /* device allocation failed */
+#define LESASM_E_HIP -4              /* a HIP runtime call failed (text in message) */
+#define LESASM_E_STATE -5            /* wrong current device, or object in wrong state */
+#define LESASM_E_NONFINITE -6        /* NaN/Inf found by the optional input check */
+#define LESASM_E_UNSUPPORTED -7      /* option value not available */
+
+/* ---- element types (value = number of nodes) --------------------------- */
+#define LESASM_TET04 4
+#define LESASM_PYR05 5
+#define LESASM_PEN06 6
+#define LESASM_HEX08 8
+
+/* ---- mesh creation flags ----------------------------------------------- */
+#define LESASM_MESH_SCATTER_ATOMIC 0u /* scatter with FP64 device atomics (default) */
+#define LESASM_MESH_SCATTER_COLOUR 1u /* greedy element colouring; plain, deterministic scatter */
+#define LESASM_MESH_KEEP_ORDER 2u     /* keep the user's element and node order within each type */
+
+typedef struct lesasm_mesh lesasm_mesh;
+
+/* Host description of a mesh.  All arrays are host memory, read during
+ * lesasm_mesh_create only (the library keeps its own device copies).
+ *   n_nodes        geometry nodes; coords[n_nodes][3] (x, y, z).
+ *   n_elems        elements; types[n_elems] in {4, 5, 6, 8}.
+ *   conn_offsets   [n_elems + 1], conn_offsets[0] = 0, each span = node count.
+ *   conn           geometry node ids, 0-based, element node order above.
+ *   field_node     [n_nodes] or NULL: unknown (field) node of each geometry
+ *                  node, in [0, n_field_nodes).  Periodic copies of a node map
+ *                  to the same field node.  NULL means the identity and
+ *                  n_field_nodes = n_nodes.
+ *   vreman_c       Vreman constant c (nu_t = c sqrt(B_beta / alpha:alpha)).
+ *   flags          LESASM_MESH_* bits.                                       */
+typedef struct lesasm_mesh_desc {
+    int64_t n_nodes;
+    const double *coords;
+    int64_t n_elems;
+    const uint8_t *types;
+    const int64_t *conn_offsets;
+    const int32_t *conn;
+    const int32_t *field_node;
+    int64_t n_field_nodes;
+    double vreman_c;
+    uint32_t flags;
+} lesasm_mesh_desc;
+
+typedef struct lesasm_mesh_info {
+    int64_t n_nodes;          /* geometry nodes */
+    int64_t n_field_nodes;    /* unknowns per component */
+    int64_t n_elems;
+    int64_t n_per_type[4];    /* TET04, PYR05, PEN06, HEX08 */
+    int32_t n_colours[4];     /* per type; 0 unless LESASM_MESH_SCATTER_COLOUR */
+    int32_t device;           /* HIP device the mesh lives on */
+    uint32_t flags;
+    uint64_t device_bytes;    /* device memory owned by the mesh */
+} lesasm_mesh_info;
+
+/* Upload and preprocess a mesh on the current HIP device (Section 3.4.3:
+ * elements are grouped by type into categories; within a category they are
+ * sorted along a Morton curve of their centroids, and nodes are renumbered in
+ * first-touch order of that element sequence).  Computes on the GPU, once:
+ * det J at every Gauss point (must be > 0), Delta_e and the lumped mass.
+ * Synchronises the device before returning.
+ * Errors: LESASM_E_INVALID_ARG, LESASM_E_INVERTED_ELEMENT, LESASM_E_OOM,
+ * LESASM_E_HIP.  On error *out is NULL and nothing is leaked.               */
+int lesasm_mesh_create(const lesasm_mesh_desc *desc, lesasm_mesh **out);
+
+/* Free a mesh and its device memory (synchronises its device).  NULL is a no-op. */
+int lesasm_mesh_destroy(lesasm_mesh *mesh);
+
+int lesasm_mesh_get_info(const lesasm_mesh *mesh, lesasm_mesh_info *info);
+
+/* Field arrays passed to the assembly are in the mesh's INTERNAL node order.
+ * perm[k] (host, n_field_nodes entries) = user field node of internal node k. */
+int lesasm_mesh_node_permutation(const lesasm_mesh *mesh, int32_t *perm);
+
+/* perm[k] (host, n_elems entries) = user element of internal element k. */
+int lesasm_mesh_element_permutation(const lesasm_mesh *mesh, int64_t *perm);
+
+/* Reorder a device field of ncomp doubles per node between user and internal
+ * order (out-of-place; `in` and `out` must not overlap).
+ *   to_internal: out[k][c] = in[perm[k]][c];  to_user: out[perm[k]][c] = in[k][c]. */
+int lesasm_fields_to_internal(const lesasm_mesh *mesh, const double *d_user, double *d_internal,
+                              int ncomp, void *stream);
+int lesasm_fields_to_user(const lesasm_mesh *mesh, const double *d_internal, double *d_user,
+                          int ncomp, void *stream);
+
+/* Copy the row-sum lumped mass M_L[n_field_nodes] (internal order) into a
+ * caller device buffer. */
+int lesasm_mesh_lumped_mass(const lesasm_mesh *mesh, double *d_out, void *stream);
+
+/* Copy Delta_e[n_elems] (internal element order) into a caller device buffer. */
+int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *stream);
+
+/* ---- per-mesh options used by lesasm_assemble_momentum_rhs ------------- */
+#define LESASM_OPT_PRECISION 1    /* LESASM_PREC_FP64 (default) or LESASM_PREC_FP32 */
+#define LESASM_OPT_RHS_MODE 2     /* LESASM_RHS_RESIDUAL (default) or LESASM_RHS_INCREMENT */
+#define LESASM_OPT_CHECK_FINITE 3 /* 1: scan u and p for NaN/Inf first (synchronises) */
+#define LESASM_OPT_BLOCK 4        /* threads per block of the assembly kernels: 64, 128 or 256 */
+#define LESASM_OPT_PROFILE 5      /* 1: record HIP events around every kernel launch */
+
+#define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
+#define LESASM_PREC_FP32 1 /* element contractions in FP32 on origin- and mean-shifted
+                              data; gather, nodal accumulation and output stay FP64 */
+#define LESASM_RHS_RESIDUAL 0  /* d_rhs = rhs (right-hand side of M_L du/dt = rhs) */
+#define LESASM_RHS_INCREMENT 1 /* d_rhs = dt * M_L^{-1} rhs */
+
+int lesasm_mesh_set_option(lesasm_mesh *mesh, int option, int64_t value);
+int lesasm_mesh_get_option(const lesasm_mesh *mesh, int option, int64_t *value);
+
+/* One explicit momentum-residual assembly (Algorithm 1, "Element assembly",
+ * once per Runge-Kutta stage):
+ *   d_u    device [n_field_nodes][3] velocity, internal order, read only.
+ *   d_p    device [n_field_nodes] modified pressure, or NULL to drop grad p.
+ *   nu     kinematic viscosity.
+ *   dt     time step; used only in LESASM_RHS_INCREMENT mode.
+ *   d_rhs  device [n_field_nodes][3], overwritten (zero-filled on the stream
+ *          first, then scatter-added).  Must not alias d_u or d_p.
+ * Pointers must be 8-byte aligned.  Asynchronous on `stream`; a kernel fault
+ * shows at the caller's next synchronisation.
+ * Errors: LESASM_E_INVALID_ARG, LESASM_E_STATE (current device differs from
+ * the mesh's), LESASM_E_NONFINITE (only with LESASM_OPT_CHECK_FINITE),
+ * LESASM_E_HIP (launch failure).                                            */
+int lesasm_assemble_momentum_rhs(lesasm_mesh *mesh, const double *d_u, const double *d_p, double nu,
+                                 double dt, double *d_rhs, void *stream);
+
+/* Kernel slots reported by lesasm_mesh_kernel_times. */
+#define LESASM_KERNEL_FILL 0      /* zero-fill of rhs */
+#define LESASM_KERNEL_TET04 1     /* element kernels, one slot per type */
+#define LESASM_KERNEL_PYR05 2
+#define LESASM_KERNEL_PEN06 3
+#define LESASM_KERNEL_HEX08 4
+#define LESASM_KERNEL_INCREMENT 5 /* dt M_L^-1 scaling */
+#define LESASM_NUM_KERNEL_SLOTS 6
+
+/* Per-slot sums of kernel durations (milliseconds, from HIP events recorded on
+ * the caller's stream while LESASM_OPT_PROFILE is 1) and launch counts since
+ * the last reset.  In colour mode one launch per colour is counted.  Waits for
+ * the recorded events (host synchronisation).  ms[] and launches[] are host
+ * arrays of LESASM_NUM_KERNEL_SLOTS entries; reset != 0 clears the sums.     */
+int lesasm_mesh_kernel_times(lesasm_mesh *mesh, double *ms, int64_t *launches, int reset);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *lesasm_last_error(void);
+
+int lesasm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LESASM_H */

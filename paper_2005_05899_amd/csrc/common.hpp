@@ -1,0 +1,98 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lesasm.h"
+
+namespace lesasm {
+
+// Brackets one kernel launch with HIP events when the mesh profiles.
+struct ProfileScope {
+    lesasm_mesh *m;
+    int slot;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfileScope(lesasm_mesh *m_, int slot_, hipStream_t s_);
+    ~ProfileScope();
+};
+
+// ---- error model: status code + thread-local message ----------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define LESASM_HIP_TRY(expr)                                                                      \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return ::lesasm::fail(e_ == hipErrorOutOfMemory ? LESASM_E_OOM : LESASM_E_HIP,        \
+                                  std::string(#expr) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+// ---- element categories ----------------------------------------------------
+// Category slot k holds type kTypes[k]; the order is also the launch order.
+constexpr int kNumCat = 4;
+constexpr int kTypes[kNumCat] = {LESASM_TET04, LESASM_PYR05, LESASM_PEN06, LESASM_HEX08};
+
+inline int cat_of_type(int t) {
+    switch (t) {
+    case LESASM_TET04: return 0;
+    case LESASM_PYR05: return 1;
+    case LESASM_PEN06: return 2;
+    case LESASM_HEX08: return 3;
+    default: return -1;
+    }
+}
+
+struct Category {
+    int type = 0;
+    int64_t n = 0;                    // elements of this type
+    int64_t first = 0;                // first internal element id of the category
+    int32_t *d_cg = nullptr;          // geometry node ids, slot-major [nnode][n]
+    int32_t *d_cf = nullptr;          // field node ids, slot-major (aliases d_cg if identical)
+    double *d_delta = nullptr;        // filter width per element
+    std::vector<int64_t> colour_off;  // colour c = elements [colour_off[c], colour_off[c+1])
+};
+
+// Arguments of one assembly launch over a contiguous element range of a category.
+struct CatView {
+    const int32_t *cg;
+    const int32_t *cf;
+    const double *delta;
+    int32_t ld;   // elements in the category (leading dimension of cg / cf)
+    int32_t off;  // first element of the range
+    int32_t n;    // elements in the range
+};
+
+}  // namespace lesasm
+
+struct lesasm_mesh {
+    int device = 0;
+    uint32_t flags = 0;
+    int64_t n_nodes = 0, n_field = 0, n_elems = 0;
+    double vreman_c = 0.1;
+    double *d_xyz = nullptr;      // [n_nodes][3], internal geometry order
+    double *d_mass = nullptr;     // [n_field], internal field order
+    int32_t *d_fperm = nullptr;   // internal -> user field node
+    double *d_delta = nullptr;    // [n_elems] filter width, internal element order
+    int *d_flag = nullptr;        // small status word for checks
+    std::vector<int32_t> h_fperm;
+    std::vector<int64_t> h_eperm;
+    lesasm::Category cat[lesasm::kNumCat];
+    std::vector<void *> allocs;
+    uint64_t bytes = 0;
+    // options
+    int precision = LESASM_PREC_FP64;
+    int rhs_mode = LESASM_RHS_RESIDUAL;
+    int check_finite = 0;
+    int block = 256;
+    int profile = 0;
+    // profiling: events pending per kernel slot, accumulated times and counts
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[LESASM_NUM_KERNEL_SLOTS];
+    double prof_ms[LESASM_NUM_KERNEL_SLOTS] = {0};
+    int64_t prof_n[LESASM_NUM_KERNEL_SLOTS] = {0};
+};

@@ -1,0 +1,181 @@
+// Device-side element computation: gather, geometry, interpolation, Vreman,
+// residual contraction (Algorithm 1 "Element assembly"; Section 3.4.3
+// gather / computation / scatter).
+//
+// One thread owns one element; its node data and residual live in registers.
+// Loops over nodes are unrolled; the Gauss-point loop is not (tables come from
+// constant memory through scalar loads), so only one point's temporaries are
+// live at a time.  Coordinates, velocities and pressures are shifted by the
+// values at local node 0 (in FP64) before the contraction precision R is
+// applied: gradients are unchanged (the reference derivatives sum to zero)
+// and in FP32 the shift removes the cancellation of absolute coordinates.
+#pragma once
+
+#include "common.hpp"
+#include "refelem.hpp"
+
+namespace lesasm {
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap so that XCD x processes a contiguous run of element blocks, which
+// keeps the nodes shared by neighbouring blocks in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, slot = b / X;
+    return x * q + (x < r ? x : r) + slot;
+}
+
+template <int T, typename R> struct ElementData {
+    static constexpr int nn = Ref<T>::nn;
+    int fid[nn];        // field node ids (scatter targets)
+    R x[nn][3];         // coordinates relative to node 0
+    R du[nn][3];        // velocity relative to node 0
+    R dp[nn];           // pressure relative to node 0
+    double u0[3];       // velocity at node 0
+};
+
+template <int T, typename R, bool HAS_P>
+__device__ __forceinline__ void gather(ElementData<T, R> &d, const CatView &c, int e,
+                                       const double *__restrict__ xyz, const double *__restrict__ u,
+                                       const double *__restrict__ p) {
+    constexpr int nn = Ref<T>::nn;
+    int gid[nn];
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        gid[a] = c.cg[(size_t)a * c.ld + e];
+        d.fid[a] = (c.cf == c.cg) ? gid[a] : c.cf[(size_t)a * c.ld + e];
+    }
+    double x0[3], p0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        x0[k] = xyz[3 * (size_t)gid[0] + k];
+        d.u0[k] = u[3 * (size_t)d.fid[0] + k];
+    }
+    if (HAS_P) p0 = p[d.fid[0]];
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            d.x[a][k] = a ? (R)(xyz[3 * (size_t)gid[a] + k] - x0[k]) : (R)0;
+            d.du[a][k] = a ? (R)(u[3 * (size_t)d.fid[a] + k] - d.u0[k]) : (R)0;
+        }
+        d.dp[a] = (HAS_P && a) ? (R)(p[d.fid[a]] - p0) : (R)0;
+    }
+}
+
+// Vreman: with alpha = G^T, beta = Delta^2 G G^T and alpha:alpha = tr(G G^T).
+// nu_t = c Delta^2 sqrt(B'/A) with B' the sum of the principal 2x2 minors of
+// G G^T (B_beta = Delta^4 B') and A its trace; 0 when A = 0; B' clamped at 0.
+template <typename R>
+__device__ __forceinline__ R vreman_nut(const R G[3][3], R cd2) {
+    const R m00 = G[0][0] * G[0][0] + G[0][1] * G[0][1] + G[0][2] * G[0][2];
+    const R m11 = G[1][0] * G[1][0] + G[1][1] * G[1][1] + G[1][2] * G[1][2];
+    const R m22 = G[2][0] * G[2][0] + G[2][1] * G[2][1] + G[2][2] * G[2][2];
+    const R m01 = G[0][0] * G[1][0] + G[0][1] * G[1][1] + G[0][2] * G[1][2];
+    const R m02 = G[0][0] * G[2][0] + G[0][1] * G[2][1] + G[0][2] * G[2][2];
+    const R m12 = G[1][0] * G[2][0] + G[1][1] * G[2][1] + G[1][2] * G[2][2];
+    const R A = m00 + m11 + m22;
+    R B = m00 * m11 - m01 * m01 + m00 * m22 - m02 * m02 + m11 * m22 - m12 * m12;
+    B = B > (R)0 ? B : (R)0;
+    return A > (R)0 ? cd2 * sqrt(B / A) : (R)0;
+}
+
+// Residual of one element into acc[a][i] (acc is zeroed here).
+// Per Gauss point: J = sum_a x_a (x) dN_a, adj(J), det; reference gradients
+// Gx = sum_a du_a (x) dN_a and px; physical G = Gx adj / det, grad p likewise;
+// u_g = u0 + sum_a N_a du_a; nu_t; S = G + G^T; C = S u_g + tr(G) u_g;
+// f = w det (C + grad p); T = w (nu + nu_t) S adj^T  (= dV sigma J^-T);
+// acc[a] -= N_a f + T dN_a.
+template <int T, typename R, bool HAS_P>
+__device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R nu, R cd2,
+                                                 R acc[Ref<T>::nn][3]) {
+    using E = Ref<T>;
+    constexpr int nn = E::nn;
+    const auto &tab = RefConst<T>::tab();
+#pragma unroll
+    for (int a = 0; a < nn; ++a) acc[a][0] = acc[a][1] = acc[a][2] = (R)0;
+
+#pragma unroll 1
+    for (int g = 0; g < E::ng; ++g) {
+        R J[3][3], Gx[3][3], px[3], ug[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ug[i] = (R)d.u0[i];
+            px[i] = (R)0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) J[i][k] = Gx[i][k] = (R)0;
+        }
+#pragma unroll
+        for (int a = 1; a < nn; ++a) {  // node 0 contributes zero after the shift
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const R dn = (R)tab.dN[g][a][k];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    J[i][k] += d.x[a][i] * dn;
+                    Gx[i][k] += d.du[a][i] * dn;
+                }
+                if (HAS_P) px[k] += d.dp[a] * dn;
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ug[i] += (R)tab.N[g][a] * d.du[a][i];
+        }
+        // adjugate: adj = det * J^-1
+        R adj[3][3];
+        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+        const R rdet = (R)1 / det;
+
+        R G[3][3], q[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                G[i][j] = (Gx[i][0] * adj[0][j] + Gx[i][1] * adj[1][j] + Gx[i][2] * adj[2][j]) * rdet;
+            q[i] = HAS_P ? (px[0] * adj[0][i] + px[1] * adj[1][i] + px[2] * adj[2][i]) * rdet : (R)0;
+        }
+        const R nut = vreman_nut<R>(G, cd2);
+
+        R S[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) S[i][j] = G[i][j] + G[j][i];
+        const R divu = G[0][0] + G[1][1] + G[2][2];
+        const R wdet = (R)tab.w[g] * det;
+        const R wvis = (R)tab.w[g] * (nu + nut);
+        R f[3], Tm[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const R C = S[i][0] * ug[0] + S[i][1] * ug[1] + S[i][2] * ug[2] + divu * ug[i];
+            f[i] = wdet * (C + q[i]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                Tm[i][k] = wvis * (S[i][0] * adj[k][0] + S[i][1] * adj[k][1] + S[i][2] * adj[k][2]);
+        }
+#pragma unroll
+        for (int a = 0; a < nn; ++a) {
+            const R Na = (R)tab.N[g][a];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                R s = Na * f[i];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    s += (R)tab.dN[g][a][k] * Tm[i][k];
+                }
+                acc[a][i] -= s;
+            }
+        }
+    }
+}
+
+}  // namespace lesasm

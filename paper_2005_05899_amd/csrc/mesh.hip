@@ -1,0 +1,488 @@
+// Mesh upload and one-time preprocessing (the library's side of Section 3.4.3):
+// validation, grouping of elements into categories (one per element type and
+// integration rule), Morton ordering of elements inside a category, first-touch
+// renumbering of nodes, optional greedy colouring, device upload, and a
+// geometry kernel that checks det J > 0 at every Gauss point and computes the
+// filter width Delta_e = V_e^(1/3) and the row-sum lumped mass (the
+// mass-matrix listing of Section 3.4.3, summed over each row).
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "element.hpp"
+
+namespace lesasm {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_error = msg;
+    return code;
+}
+
+// ---- geometry kernel -------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_geometry(CatView c, int first, const double *__restrict__ xyz,
+                                                  double *__restrict__ mass, double *__restrict__ delta,
+                                                  int *__restrict__ bad) {
+    using E = Ref<T>;
+    constexpr int nn = E::nn;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= c.n) return;
+    double x[nn][3];
+    int fid[nn];
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        const int g = c.cg[(size_t)a * c.ld + e];
+        fid[a] = c.cf[(size_t)a * c.ld + e];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[a][k] = xyz[3 * (size_t)g + k];
+    }
+#pragma unroll
+    for (int a = nn - 1; a >= 0; --a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[a][k] -= x[0][k];
+    double vol = 0.0, m[nn];
+#pragma unroll
+    for (int a = 0; a < nn; ++a) m[a] = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int g = 0; g < E::ng; ++g) {
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int a = 1; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) J[i][k] += x[a][i] * E::tab.dN[g][a][k];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        ok = ok && (det > 0.0);
+        const double dv = E::tab.w[g] * det;
+        vol += dv;
+#pragma unroll
+        for (int a = 0; a < nn; ++a) m[a] += dv * E::tab.N[g][a];
+    }
+    if (!ok) atomicMin(bad, first + e);
+    delta[e] = cbrt(vol);
+#pragma unroll
+    for (int a = 0; a < nn; ++a) unsafeAtomicAdd(mass + fid[a], m[a]);
+}
+
+__global__ void k_permute(const double *__restrict__ in, double *__restrict__ out, const int32_t *__restrict__ perm,
+                          size_t n, int nc, int to_internal) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n * nc; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = t / nc;
+        const int c = (int)(t - k * nc);
+        const size_t uidx = (size_t)perm[k] * nc + c;
+        if (to_internal)
+            out[t] = in[uidx];
+        else
+            out[uidx] = in[t];
+    }
+}
+
+int grid_for(size_t n, int block);
+
+// ---- host helpers ------------------------------------------------------------
+template <class T> static int dalloc(lesasm_mesh *m, T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return LESASM_OK;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LESASM_E_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed: " +
+                                      hipGetErrorString(e));
+    }
+    m->allocs.push_back(q);
+    m->bytes += n * sizeof(T);
+    *p = (T *)q;
+    return LESASM_OK;
+}
+
+template <class T> static int upload(lesasm_mesh *m, T **p, const std::vector<T> &h) {
+    int st = dalloc(m, p, h.size());
+    if (st) return st;
+    if (!h.empty()) LESASM_HIP_TRY(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return LESASM_OK;
+}
+
+static uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit of 63
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+static void free_mesh(lesasm_mesh *m) {
+    if (!m) return;
+    for (auto &v : m->pending)
+        for (auto &ev : v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    int cur = 0;
+    bool have = hipGetDevice(&cur) == hipSuccess;
+    if (!m->allocs.empty()) {
+        (void)hipSetDevice(m->device);
+        (void)hipDeviceSynchronize();
+        for (void *p : m->allocs) (void)hipFree(p);
+        if (have) (void)hipSetDevice(cur);
+    }
+    delete m;
+}
+
+struct MeshGuard {
+    lesasm_mesh *m;
+    ~MeshGuard() { free_mesh(m); }
+};
+
+// Greedy colouring of the elements `order` (user ids) on their field nodes:
+// each element takes the lowest colour not used by any element sharing a node.
+static std::vector<int> greedy_colour(const std::vector<int64_t> &order, const int64_t *offs, const int32_t *conn,
+                                      const int32_t *fmap, int64_t n_field, int &ncol) {
+    constexpr int W = 4;  // up to 256 colours
+    std::vector<uint64_t> used((size_t)n_field * W, 0);
+    std::vector<int> col(order.size());
+    ncol = 0;
+    for (size_t j = 0; j < order.size(); ++j) {
+        const int64_t e = order[j];
+        uint64_t forb[W] = {0, 0, 0, 0};
+        for (int64_t q = offs[e]; q < offs[e + 1]; ++q) {
+            const int64_t f = fmap ? fmap[conn[q]] : conn[q];
+            for (int w = 0; w < W; ++w) forb[w] |= used[(size_t)f * W + w];
+        }
+        int c = -1;
+        for (int w = 0; w < W && c < 0; ++w)
+            if (~forb[w]) c = 64 * w + __builtin_ctzll(~forb[w]);
+        if (c < 0) return {};
+        col[j] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int64_t q = offs[e]; q < offs[e + 1]; ++q) {
+            const int64_t f = fmap ? fmap[conn[q]] : conn[q];
+            used[(size_t)f * W + c / 64] |= 1ULL << (c % 64);
+        }
+    }
+    return col;
+}
+
+}  // namespace lesasm
+
+using namespace lesasm;
+
+extern "C" const char *lesasm_last_error(void) { return g_error.c_str(); }
+
+extern "C" int lesasm_version(void) { return LESASM_VERSION; }
+
+extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) {
+    if (!out) return fail(LESASM_E_INVALID_ARG, "mesh_create: out is NULL");
+    *out = nullptr;
+    if (!d) return fail(LESASM_E_INVALID_ARG, "mesh_create: desc is NULL");
+    const int64_t nn = d->n_nodes, ne = d->n_elems;
+    if (nn < 0 || ne < 0 || nn >= INT32_MAX || ne >= INT32_MAX)
+        return fail(LESASM_E_INVALID_ARG, "mesh_create: node or element count out of range");
+    if (ne > 0 && (!d->types || !d->conn_offsets || !d->conn))
+        return fail(LESASM_E_INVALID_ARG, "mesh_create: types, conn_offsets or conn is NULL");
+    if (nn > 0 && !d->coords) return fail(LESASM_E_INVALID_ARG, "mesh_create: coords is NULL");
+    if (d->flags & ~(LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_KEEP_ORDER))
+        return fail(LESASM_E_INVALID_ARG, "mesh_create: unknown flag bits");
+    if (!(d->vreman_c >= 0.0)) return fail(LESASM_E_INVALID_ARG, "mesh_create: vreman_c must be >= 0");
+    const int32_t *fmap = d->field_node;
+    const int64_t nf = fmap ? d->n_field_nodes : nn;
+    if (fmap) {
+        if (nf <= 0 || nf > nn) return fail(LESASM_E_INVALID_ARG, "mesh_create: n_field_nodes out of range");
+        for (int64_t g = 0; g < nn; ++g)
+            if (fmap[g] < 0 || fmap[g] >= nf)
+                return fail(LESASM_E_INVALID_ARG, "mesh_create: field_node[" + std::to_string(g) + "] out of range");
+    }
+    if (ne > 0 && d->conn_offsets[0] != 0) return fail(LESASM_E_INVALID_ARG, "mesh_create: conn_offsets[0] != 0");
+    std::vector<int64_t> order[kNumCat];
+    for (int64_t e = 0; e < ne; ++e) {
+        const int t = d->types[e];
+        const int k = cat_of_type(t);
+        if (k < 0)
+            return fail(LESASM_E_INVALID_ARG, "mesh_create: element " + std::to_string(e) + " has type " +
+                                                  std::to_string(t));
+        if (d->conn_offsets[e + 1] - d->conn_offsets[e] != t)
+            return fail(LESASM_E_INVALID_ARG, "mesh_create: element " + std::to_string(e) + " has a wrong node count");
+        for (int64_t q = d->conn_offsets[e]; q < d->conn_offsets[e + 1]; ++q)
+            if (d->conn[q] < 0 || d->conn[q] >= nn)
+                return fail(LESASM_E_INVALID_ARG, "mesh_create: element " + std::to_string(e) +
+                                                      " references node " + std::to_string(d->conn[q]));
+        order[k].push_back(e);
+    }
+
+    lesasm_mesh *m = new lesasm_mesh();
+    MeshGuard guard{m};
+    LESASM_HIP_TRY(hipGetDevice(&m->device));
+    m->flags = d->flags;
+    m->n_nodes = nn;
+    m->n_field = nf;
+    m->n_elems = ne;
+    m->vreman_c = d->vreman_c;
+    const bool keep = d->flags & LESASM_MESH_KEEP_ORDER;
+    const bool colour = d->flags & LESASM_MESH_SCATTER_COLOUR;
+
+    // Morton order of element centroids inside each category
+    if (!keep && ne > 0) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t g = 0; g < nn; ++g)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], d->coords[3 * g + k]);
+                hi[k] = std::max(hi[k], d->coords[3 * g + k]);
+            }
+        double scale[3];
+        for (int k = 0; k < 3; ++k) scale[k] = hi[k] > lo[k] ? (double)((1 << 21) - 1) / (hi[k] - lo[k]) : 0.0;
+        for (int k = 0; k < kNumCat; ++k) {
+            std::vector<std::pair<uint64_t, int64_t>> key(order[k].size());
+            for (size_t j = 0; j < order[k].size(); ++j) {
+                const int64_t e = order[k][j];
+                double c[3] = {0, 0, 0};
+                const int64_t o = d->conn_offsets[e], n = d->conn_offsets[e + 1] - o;
+                for (int64_t a = 0; a < n; ++a)
+                    for (int q = 0; q < 3; ++q) c[q] += d->coords[3 * (int64_t)d->conn[o + a] + q];
+                uint64_t code = 0;
+                for (int q = 0; q < 3; ++q)
+                    code |= spread3((uint64_t)((c[q] / n - lo[q]) * scale[q])) << q;
+                key[j] = {code, e};
+            }
+            std::sort(key.begin(), key.end());
+            for (size_t j = 0; j < key.size(); ++j) order[k][j] = key[j].second;
+        }
+    }
+
+    // colour schedule: stable regroup by colour inside each category
+    if (colour) {
+        for (int k = 0; k < kNumCat; ++k) {
+            int ncol = 0;
+            std::vector<int> col = greedy_colour(order[k], d->conn_offsets, d->conn, fmap, nf, ncol);
+            if (col.empty() && !order[k].empty())
+                return fail(LESASM_E_UNSUPPORTED, "mesh_create: more than 256 colours needed");
+            std::vector<int64_t> cnt(ncol + 1, 0);
+            for (int c : col) cnt[c + 1]++;
+            for (int c = 0; c < ncol; ++c) cnt[c + 1] += cnt[c];
+            std::vector<int64_t> reordered(order[k].size());
+            std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+            for (size_t j = 0; j < col.size(); ++j) reordered[pos[col[j]]++] = order[k][j];
+            order[k].swap(reordered);
+            m->cat[k].colour_off = cnt;
+        }
+    }
+
+    // internal element order and first-touch node numbering
+    m->h_eperm.reserve(ne);
+    int64_t first = 0;
+    for (int k = 0; k < kNumCat; ++k) {
+        m->cat[k].type = kTypes[k];
+        m->cat[k].n = (int64_t)order[k].size();
+        m->cat[k].first = first;
+        first += m->cat[k].n;
+        m->h_eperm.insert(m->h_eperm.end(), order[k].begin(), order[k].end());
+    }
+    std::vector<int32_t> gnew(nn, -1), fnew(nf, -1);
+    if (keep) {
+        std::iota(gnew.begin(), gnew.end(), 0);
+        std::iota(fnew.begin(), fnew.end(), 0);
+    } else {
+        int32_t ng = 0, nfc = 0;
+        for (int64_t e : m->h_eperm)
+            for (int64_t q = d->conn_offsets[e]; q < d->conn_offsets[e + 1]; ++q) {
+                const int32_t g = d->conn[q];
+                if (gnew[g] < 0) gnew[g] = ng++;
+                const int32_t f = fmap ? fmap[g] : g;
+                if (fnew[f] < 0) fnew[f] = nfc++;
+            }
+        for (int64_t g = 0; g < nn; ++g)
+            if (gnew[g] < 0) gnew[g] = ng++;
+        for (int64_t f = 0; f < nf; ++f)
+            if (fnew[f] < 0) fnew[f] = nfc++;
+    }
+    m->h_fperm.assign(nf, 0);
+    for (int64_t f = 0; f < nf; ++f) m->h_fperm[fnew[f]] = (int32_t)f;
+    // without a field map the two numberings coincide, so one index array serves both
+    const bool alias = (fmap == nullptr);
+
+    int st;
+    {
+        std::vector<double> xyz((size_t)3 * nn);
+        for (int64_t g = 0; g < nn; ++g)
+            for (int k = 0; k < 3; ++k) xyz[3 * (size_t)gnew[g] + k] = d->coords[3 * g + k];
+        if ((st = upload(m, &m->d_xyz, xyz))) return st;
+    }
+    if ((st = upload(m, &m->d_fperm, m->h_fperm))) return st;
+    if ((st = dalloc(m, &m->d_mass, (size_t)nf))) return st;
+    if ((st = dalloc(m, &m->d_flag, 4))) return st;
+    if ((st = dalloc(m, &m->d_delta, (size_t)ne))) return st;
+    for (int k = 0; k < kNumCat; ++k) {
+        Category &c = m->cat[k];
+        if (c.n == 0) continue;
+        const int nnode = c.type;
+        std::vector<int32_t> cg((size_t)nnode * c.n), cf;
+        if (!alias) cf.resize(cg.size());
+        for (int64_t j = 0; j < c.n; ++j) {
+            const int64_t e = order[k][j];
+            for (int a = 0; a < nnode; ++a) {
+                const int32_t g = d->conn[d->conn_offsets[e] + a];
+                cg[(size_t)a * c.n + j] = gnew[g];
+                if (!alias) cf[(size_t)a * c.n + j] = fnew[fmap[g]];
+            }
+        }
+        if ((st = upload(m, &c.d_cg, cg))) return st;
+        if (alias)
+            c.d_cf = c.d_cg;
+        else if ((st = upload(m, &c.d_cf, cf)))
+            return st;
+        c.d_delta = m->d_delta + c.first;
+    }
+
+    // geometry: det J check, Delta_e, lumped mass
+    if (nf > 0) LESASM_HIP_TRY(hipMemset(m->d_mass, 0, sizeof(double) * nf));
+    const int big = INT_MAX;
+    LESASM_HIP_TRY(hipMemcpy(m->d_flag, &big, sizeof(int), hipMemcpyHostToDevice));
+    for (int k = 0; k < kNumCat; ++k) {
+        Category &c = m->cat[k];
+        if (c.n == 0) continue;
+        CatView v{c.d_cg, c.d_cf, c.d_delta, (int32_t)c.n, 0, (int32_t)c.n};
+        const dim3 grid((unsigned)((c.n + 255) / 256)), block(256);
+        switch (c.type) {
+        case LESASM_TET04: hipLaunchKernelGGL(k_geometry<LESASM_TET04>, grid, block, 0, 0, v, (int)c.first, m->d_xyz, m->d_mass, c.d_delta, m->d_flag); break;
+        case LESASM_PYR05: hipLaunchKernelGGL(k_geometry<LESASM_PYR05>, grid, block, 0, 0, v, (int)c.first, m->d_xyz, m->d_mass, c.d_delta, m->d_flag); break;
+        case LESASM_PEN06: hipLaunchKernelGGL(k_geometry<LESASM_PEN06>, grid, block, 0, 0, v, (int)c.first, m->d_xyz, m->d_mass, c.d_delta, m->d_flag); break;
+        case LESASM_HEX08: hipLaunchKernelGGL(k_geometry<LESASM_HEX08>, grid, block, 0, 0, v, (int)c.first, m->d_xyz, m->d_mass, c.d_delta, m->d_flag); break;
+        }
+        LESASM_HIP_TRY(hipGetLastError());
+    }
+    LESASM_HIP_TRY(hipDeviceSynchronize());
+    int bad = big;
+    LESASM_HIP_TRY(hipMemcpy(&bad, m->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (bad != big)
+        return fail(LESASM_E_INVERTED_ELEMENT, "mesh_create: element " + std::to_string(m->h_eperm[bad]) +
+                                                   " has det J <= 0 at a Gauss point");
+    guard.m = nullptr;
+    *out = m;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_destroy(lesasm_mesh *m) {
+    free_mesh(m);
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_get_info(const lesasm_mesh *m, lesasm_mesh_info *info) {
+    if (!m || !info) return fail(LESASM_E_INVALID_ARG, "get_info: NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_nodes = m->n_nodes;
+    info->n_field_nodes = m->n_field;
+    info->n_elems = m->n_elems;
+    for (int k = 0; k < kNumCat; ++k) {
+        info->n_per_type[k] = m->cat[k].n;
+        info->n_colours[k] = m->cat[k].colour_off.empty() ? 0 : (int32_t)m->cat[k].colour_off.size() - 1;
+    }
+    info->device = m->device;
+    info->flags = m->flags;
+    info->device_bytes = m->bytes;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_node_permutation(const lesasm_mesh *m, int32_t *perm) {
+    if (!m || (!perm && m->n_field > 0)) return fail(LESASM_E_INVALID_ARG, "node_permutation: NULL argument");
+    if (m->n_field) std::memcpy(perm, m->h_fperm.data(), sizeof(int32_t) * m->n_field);
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_element_permutation(const lesasm_mesh *m, int64_t *perm) {
+    if (!m || (!perm && m->n_elems > 0)) return fail(LESASM_E_INVALID_ARG, "element_permutation: NULL argument");
+    if (m->n_elems) std::memcpy(perm, m->h_eperm.data(), sizeof(int64_t) * m->n_elems);
+    return LESASM_OK;
+}
+
+static int permute(const lesasm_mesh *m, const double *in, double *out, int nc, void *stream, int to_internal) {
+    if (!m) return fail(LESASM_E_INVALID_ARG, "permute: mesh is NULL");
+    if (nc < 1 || nc > 64) return fail(LESASM_E_INVALID_ARG, "permute: ncomp must be in 1..64");
+    if (m->n_field == 0) return LESASM_OK;
+    if (!in || !out || in == out) return fail(LESASM_E_INVALID_ARG, "permute: NULL or aliased buffers");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device) return fail(LESASM_E_STATE, "permute: current device differs from the mesh's device");
+    const size_t n = (size_t)m->n_field;
+    hipLaunchKernelGGL(k_permute, dim3(grid_for(n * nc, 256)), dim3(256), 0, (hipStream_t)stream, in, out,
+                       m->d_fperm, n, nc, to_internal);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_fields_to_internal(const lesasm_mesh *m, const double *d_user, double *d_internal, int ncomp,
+                                         void *stream) {
+    return permute(m, d_user, d_internal, ncomp, stream, 1);
+}
+
+extern "C" int lesasm_fields_to_user(const lesasm_mesh *m, const double *d_internal, double *d_user, int ncomp,
+                                     void *stream) {
+    return permute(m, d_internal, d_user, ncomp, stream, 0);
+}
+
+extern "C" int lesasm_mesh_lumped_mass(const lesasm_mesh *m, double *d_out, void *stream) {
+    if (!m || (!d_out && m->n_field)) return fail(LESASM_E_INVALID_ARG, "lumped_mass: NULL argument");
+    if (m->n_field)
+        LESASM_HIP_TRY(hipMemcpyAsync(d_out, m->d_mass, sizeof(double) * m->n_field, hipMemcpyDeviceToDevice,
+                                      (hipStream_t)stream));
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_filter_width(const lesasm_mesh *m, double *d_out, void *stream) {
+    if (!m || (!d_out && m->n_elems)) return fail(LESASM_E_INVALID_ARG, "filter_width: NULL argument");
+    if (m->n_elems)
+        LESASM_HIP_TRY(hipMemcpyAsync(d_out, m->d_delta, sizeof(double) * m->n_elems, hipMemcpyDeviceToDevice,
+                                      (hipStream_t)stream));
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_set_option(lesasm_mesh *m, int option, int64_t value) {
+    if (!m) return fail(LESASM_E_INVALID_ARG, "set_option: mesh is NULL");
+    switch (option) {
+    case LESASM_OPT_PRECISION:
+        if (value != LESASM_PREC_FP64 && value != LESASM_PREC_FP32)
+            return fail(LESASM_E_UNSUPPORTED, "set_option: unknown precision");
+        m->precision = (int)value;
+        return LESASM_OK;
+    case LESASM_OPT_RHS_MODE:
+        if (value != LESASM_RHS_RESIDUAL && value != LESASM_RHS_INCREMENT)
+            return fail(LESASM_E_UNSUPPORTED, "set_option: unknown rhs mode");
+        m->rhs_mode = (int)value;
+        return LESASM_OK;
+    case LESASM_OPT_CHECK_FINITE:
+        m->check_finite = value != 0;
+        return LESASM_OK;
+    case LESASM_OPT_BLOCK:
+        if (value != 64 && value != 128 && value != 256)
+            return fail(LESASM_E_UNSUPPORTED, "set_option: block must be 64, 128 or 256");
+        m->block = (int)value;
+        return LESASM_OK;
+    case LESASM_OPT_PROFILE:
+        m->profile = value != 0;
+        return LESASM_OK;
+    default:
+        return fail(LESASM_E_INVALID_ARG, "set_option: unknown option " + std::to_string(option));
+    }
+}
+
+extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t *value) {
+    if (!m || !value) return fail(LESASM_E_INVALID_ARG, "get_option: NULL argument");
+    switch (option) {
+    case LESASM_OPT_PRECISION: *value = m->precision; return LESASM_OK;
+    case LESASM_OPT_RHS_MODE: *value = m->rhs_mode; return LESASM_OK;
+    case LESASM_OPT_CHECK_FINITE: *value = m->check_finite; return LESASM_OK;
+    case LESASM_OPT_BLOCK: *value = m->block; return LESASM_OK;
+    case LESASM_OPT_PROFILE: *value = m->profile; return LESASM_OK;
+    default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
+    }
+}

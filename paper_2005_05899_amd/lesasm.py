@@ -1,0 +1,221 @@
+"""Thin ctypes binding of the C-ABI library ``_lib/liblesasm.so``.
+
+Argument marshalling only: every step of the assembly runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors) and the current HIP
+stream.  If the library is missing this module raises on use; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (load torch's HIP runtime before the library binds to it)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblesasm.so")
+
+OK, E_INVALID_ARG, E_INVERTED_ELEMENT, E_OOM, E_HIP, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+TET04, PYR05, PEN06, HEX08 = 4, 5, 6, 8
+MESH_SCATTER_ATOMIC, MESH_SCATTER_COLOUR, MESH_KEEP_ORDER = 0, 1, 2
+OPT_PRECISION, OPT_RHS_MODE, OPT_CHECK_FINITE, OPT_BLOCK, OPT_PROFILE = 1, 2, 3, 4, 5
+KERNEL_SLOTS = ("fill", "tet04", "pyr05", "pen06", "hex08", "increment")
+PREC_FP64, PREC_FP32 = 0, 1
+RHS_RESIDUAL, RHS_INCREMENT = 0, 1
+
+# every symbol declared in include/lesasm.h
+EXPORTS = [
+    "lesasm_mesh_create", "lesasm_mesh_destroy", "lesasm_mesh_get_info", "lesasm_mesh_node_permutation",
+    "lesasm_mesh_element_permutation", "lesasm_fields_to_internal", "lesasm_fields_to_user",
+    "lesasm_mesh_lumped_mass", "lesasm_mesh_filter_width", "lesasm_mesh_set_option", "lesasm_mesh_get_option",
+    "lesasm_assemble_momentum_rhs", "lesasm_mesh_kernel_times", "lesasm_last_error", "lesasm_version",
+]
+
+
+class LesasmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lesasm error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64), ("coords", ctypes.c_void_p), ("n_elems", ctypes.c_int64),
+        ("types", ctypes.c_void_p), ("conn_offsets", ctypes.c_void_p), ("conn", ctypes.c_void_p),
+        ("field_node", ctypes.c_void_p), ("n_field_nodes", ctypes.c_int64), ("vreman_c", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64), ("n_field_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64),
+        ("n_per_type", ctypes.c_int64 * 4), ("n_colours", ctypes.c_int32 * 4), ("device", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2005_05899_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "lesasm_mesh_create": [P, P], "lesasm_mesh_destroy": [P], "lesasm_mesh_get_info": [P, P],
+        "lesasm_mesh_node_permutation": [P, P], "lesasm_mesh_element_permutation": [P, P],
+        "lesasm_fields_to_internal": [P, P, P, I, P], "lesasm_fields_to_user": [P, P, P, I, P],
+        "lesasm_mesh_lumped_mass": [P, P, P], "lesasm_mesh_filter_width": [P, P, P],
+        "lesasm_mesh_set_option": [P, I, I64], "lesasm_mesh_get_option": [P, I, P],
+        "lesasm_assemble_momentum_rhs": [P, P, P, D, D, P, P], "lesasm_mesh_kernel_times": [P, P, P, I],
+        "lesasm_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.lesasm_last_error.argtypes = []
+    lib.lesasm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != OK:
+        raise LesasmError(status, load().lesasm_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    """A mesh uploaded to the current GPU (see lesasm_mesh_create)."""
+
+    def __init__(self, coords, types, conn_offsets, conn, field_node=None, n_field_nodes=0,
+                 vreman_c: float = 0.1, colour: bool = False, keep_order: bool = False):
+        lib = load()
+        self._keep = [np.ascontiguousarray(coords, np.float64), np.ascontiguousarray(types, np.uint8),
+                      np.ascontiguousarray(conn_offsets, np.int64), np.ascontiguousarray(conn, np.int32),
+                      None if field_node is None else np.ascontiguousarray(field_node, np.int32)]
+        c, t, o, cn, fn = self._keep
+        d = MeshDesc(len(c), c.ctypes.data, len(t), t.ctypes.data, o.ctypes.data, cn.ctypes.data,
+                     None if fn is None else fn.ctypes.data, int(n_field_nodes) if fn is not None else 0,
+                     float(vreman_c), (MESH_SCATTER_COLOUR if colour else 0) | (MESH_KEEP_ORDER if keep_order else 0))
+        h = ctypes.c_void_p()
+        check(lib.lesasm_mesh_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+        info = MeshInfo()
+        check(lib.lesasm_mesh_get_info(self._h, ctypes.byref(info)))
+        self.n_nodes, self.n_field_nodes, self.n_elems = info.n_nodes, info.n_field_nodes, info.n_elems
+        self.n_per_type = dict(zip((TET04, PYR05, PEN06, HEX08), list(info.n_per_type)))
+        self.n_colours = dict(zip((TET04, PYR05, PEN06, HEX08), list(info.n_colours)))
+        self.device_index = info.device
+        self.device_bytes = info.device_bytes
+        self.device = torch.device("cuda", info.device)
+
+    @classmethod
+    def from_arrays(cls, m, vreman_c: float = 0.1, **kw) -> "Mesh":
+        """From any object with coords / types / conn_offsets / conn / field_node / n_field_nodes."""
+        return cls(m.coords, m.types, m.conn_offsets, m.conn, m.field_node, m.n_field_nodes, vreman_c, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lesasm_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- orderings ---------------------------------------------------------
+    def node_permutation(self) -> np.ndarray:
+        perm = np.empty(self.n_field_nodes, np.int32)
+        check(load().lesasm_mesh_node_permutation(self._h, perm.ctypes.data))
+        return perm
+
+    def element_permutation(self) -> np.ndarray:
+        perm = np.empty(self.n_elems, np.int64)
+        check(load().lesasm_mesh_element_permutation(self._h, perm.ctypes.data))
+        return perm
+
+    def _field(self, t, ncomp=None):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("expected a contiguous float64 tensor on the GPU")
+        if t.shape[0] != self.n_field_nodes:
+            raise ValueError(f"expected {self.n_field_nodes} rows, got {t.shape[0]}")
+        return t if ncomp is None else t
+
+    def to_internal(self, t):
+        t = self._field(t)
+        out = torch.empty_like(t)
+        nc = 1 if t.dim() == 1 else int(np.prod(t.shape[1:]))
+        check(load().lesasm_fields_to_internal(self._h, _ptr(t), _ptr(out), nc, _stream()))
+        return out
+
+    def to_user(self, t):
+        t = self._field(t)
+        out = torch.empty_like(t)
+        nc = 1 if t.dim() == 1 else int(np.prod(t.shape[1:]))
+        check(load().lesasm_fields_to_user(self._h, _ptr(t), _ptr(out), nc, _stream()))
+        return out
+
+    def lumped_mass(self):
+        out = torch.empty(self.n_field_nodes, dtype=torch.float64, device=self.device)
+        check(load().lesasm_mesh_lumped_mass(self._h, _ptr(out), _stream()))
+        return out
+
+    def filter_width(self):
+        out = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
+        check(load().lesasm_mesh_filter_width(self._h, _ptr(out), _stream()))
+        return out
+
+    # ---- options -----------------------------------------------------------
+    def set_option(self, option: int, value: int):
+        check(load().lesasm_mesh_set_option(self._h, option, int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        check(load().lesasm_mesh_get_option(self._h, option, ctypes.byref(v)))
+        return v.value
+
+    @property
+    def precision(self) -> str:
+        return "fp32" if self.get_option(OPT_PRECISION) == PREC_FP32 else "fp64"
+
+    @precision.setter
+    def precision(self, value: str):
+        self.set_option(OPT_PRECISION, {"fp64": PREC_FP64, "fp32": PREC_FP32}[value])
+
+    def kernel_times(self, reset: bool = False) -> dict:
+        """{slot: (total ms, launches)} from the events recorded with OPT_PROFILE."""
+        ms = (ctypes.c_double * len(KERNEL_SLOTS))()
+        n = (ctypes.c_int64 * len(KERNEL_SLOTS))()
+        check(load().lesasm_mesh_kernel_times(self._h, ms, n, int(reset)))
+        return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_SLOTS)}
+
+    # ---- the hot path --------------------------------------------------------
+    def assemble_momentum_rhs(self, u, p=None, nu: float = 0.0, dt: float = 0.0, out=None):
+        """rhs [n_field_nodes, 3] (internal order) of M_L du/dt = rhs for velocity
+        u [n_field_nodes, 3] and modified pressure p [n_field_nodes] (or None)."""
+        u = self._field(u)
+        if p is not None:
+            p = self._field(p)
+        if out is None:
+            out = torch.empty((self.n_field_nodes, 3), dtype=torch.float64, device=u.device)
+        check(load().lesasm_assemble_momentum_rhs(self._h, _ptr(u), _ptr(p), float(nu), float(dt), _ptr(out),
+                                                  _stream()))
+        return out
