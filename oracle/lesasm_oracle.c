@@ -483,3 +483,71 @@ int oracle_filter_width(int64_t n_nodes, const double *coords, int64_t n_elems, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pressure step operators (Algorithm 1: Laplacian assembled once before the */
+/* time loop; projection step of the fractional-step scheme, Section 3.2)   */
+/* ------------------------------------------------------------------------ */
+
+/* Element Laplacian K[a*n + b] = sum_g w_g det J_g dN_a/dx . dN_b/dx. */
+int oracle_element_laplacian(int type, const double *x, double *K)
+{
+    double pts[3 * ORACLE_MAX_GAUSS], w[ORACLE_MAX_GAUSS];
+    double N[ORACLE_MAX_NODE], dN[3 * ORACLE_MAX_NODE], dNdx[3 * ORACLE_MAX_NODE];
+    const int n = oracle_nnode(type);
+    const int ng = oracle_gauss(type, pts, w);
+    if (n < 0 || ng < 0) return -1;
+    for (int k = 0; k < n * n; ++k) K[k] = 0.0;
+    for (int q = 0; q < ng; ++q) {
+        double J[3][3], Ki[3][3];
+        oracle_shape(type, pts + 3 * q, N, dN);
+        jacobian(n, x, dN, J);
+        const double det = det3(J);
+        if (!(det > 0.0)) return -2;
+        inv3(J, det, Ki);
+        for (int a = 0; a < n; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j) s += Ki[j][i] * dN[3 * a + j];
+                dNdx[3 * a + i] = s;
+            }
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                double s = 0.0;
+                for (int i = 0; i < 3; ++i) s += dNdx[3 * a + i] * dNdx[3 * b + i];
+                K[a * n + b] += w[q] * det * s;
+            }
+    }
+    return 0;
+}
+
+/* Nodal divergence (D u)[f] = sum_e sum_g dV N_a div u, out[n_field]. */
+int oracle_divergence(int64_t n_nodes, const double *coords, int64_t n_elems, const uint8_t *types,
+                      const int64_t *offs, const int32_t *conn, const int32_t *field_node, int64_t n_field,
+                      const double *u, double *out)
+{
+    double x[3 * ORACLE_MAX_NODE], ue[3 * ORACLE_MAX_NODE], pts[3 * ORACLE_MAX_GAUSS], w[ORACLE_MAX_GAUSS];
+    double N[ORACLE_MAX_NODE], dN[3 * ORACLE_MAX_NODE];
+    int64_t fid[ORACLE_MAX_NODE];
+    g_bad_element = -1;
+    for (int64_t k = 0; k < n_field; ++k) out[k] = 0.0;
+    for (int64_t e = 0; e < n_elems; ++e) {
+        const int n = gather(e, n_nodes, coords, types, offs, conn, field_node, n_field, u, NULL, x, ue, NULL, fid);
+        if (n < 0) { g_bad_element = e; return -1; }
+        const int ng = oracle_gauss(types[e], pts, w);
+        for (int q = 0; q < ng; ++q) {
+            double J[3][3], Ki[3][3];
+            oracle_shape(types[e], pts + 3 * q, N, dN);
+            jacobian(n, x, dN, J);
+            const double det = det3(J);
+            if (!(det > 0.0)) { g_bad_element = e; return -2; }
+            inv3(J, det, Ki);
+            double div = 0.0;
+            for (int a = 0; a < n; ++a)
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) div += ue[3 * a + i] * Ki[j][i] * dN[3 * a + j];
+            for (int a = 0; a < n; ++a) out[fid[a]] += w[q] * det * N[a] * div;
+        }
+    }
+    return 0;
+}

@@ -55,6 +55,8 @@ def load():
         lib.oracle_assemble.argtypes = [i64, P, i64, P, P, P, P, i64, P, P, f64, f64, i32, P]
         lib.oracle_lumped_mass.argtypes = [i64, P, i64, P, P, P, P, i64, P]
         lib.oracle_filter_width.argtypes = [i64, P, i64, P, P, P, P]
+        lib.oracle_element_laplacian.argtypes = [i32, P, P]
+        lib.oracle_divergence.argtypes = [i64, P, i64, P, P, P, P, i64, P, P]
         lib.oracle_bad_element.restype = ctypes.c_longlong
         _lib = lib
         return lib
@@ -164,3 +166,21 @@ def filter_width(mesh) -> np.ndarray:
     d = np.zeros(len(types))
     _check(load().oracle_filter_width(len(coords), _p(coords), len(types), _p(types), _p(offs), _p(conn), _p(d)))
     return d
+
+
+def element_laplacian(t: int, x) -> np.ndarray:
+    x = _f64(x)
+    n = nnode(t)
+    K = np.zeros((n, n))
+    _check(load().oracle_element_laplacian(t, _p(x), _p(K)))
+    return K
+
+
+def divergence(mesh, u) -> np.ndarray:
+    """(D u)_a = sum over elements of int N_a div u, [n_field_nodes]."""
+    coords, types, offs, conn, fn, nf = _mesh_args(mesh)
+    u = _f64(u, (nf, 3))
+    out = np.zeros(nf)
+    _check(load().oracle_divergence(len(coords), _p(coords), len(types), _p(types), _p(offs), _p(conn), _p(fn), nf,
+                                    _p(u), _p(out)))
+    return out

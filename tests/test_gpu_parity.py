@@ -116,12 +116,17 @@ def test_single_type_meshes(torch_cuda, t):
 
 
 def test_single_element(torch_cuda):
+    """One element per type with random nodal data (a one-cell box spans a whole
+    period of the Fourier fields, which would make them constant)."""
     import oracle
     for t in (mg.TET04, mg.PYR05, mg.PEN06, mg.HEX08):
         c = mg.small_hybrid_case(nx=1, ny=1, layers=[(t, 1)], seed=30 + t)
         one = mg.Mesh(c.mesh.coords, c.mesh.types[:1], c.mesh.conn_offsets[:2], c.mesh.conn[:t])
-        case = mg.Case("one", one, c.u, c.p, 0.3, 0.1)
-        ref = oracle.assemble(one, c.u, c.p, 0.3, 0.1)
+        rng = np.random.default_rng(t)
+        u = rng.standard_normal((one.n_nodes, 3))
+        p = rng.standard_normal(one.n_nodes)
+        case = mg.Case("one", one, u, p, 0.3, 0.1)
+        ref = oracle.assemble(one, u, p, 0.3, 0.1)
         got, m = run_gpu(torch_cuda, case)
         assert_close(got, ref, TOL64, f"single {mg.TYPE_NAME[t]}")
         m.close()

@@ -12,7 +12,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lesasm_oracle.c")
 PINS = ["tests/test_oracle_refelem.py", "tests/test_oracle_vreman.py", "tests/test_oracle_exact.py",
-        "tests/test_oracle_invariants.py"]
+        "tests/test_oracle_invariants.py", "tests/test_oracle_step.py"]
 
 MUTANTS = {
     "gradient_uses_J_inverse_untransposed": ("s += K[j][i] * dN[3 * a + j];", "s += K[i][j] * dN[3 * a + j];"),
@@ -33,6 +33,10 @@ MUTANTS = {
     "scatter_wrong_node": ("rhs[3 * fid[a] + i] += R[3 * a + i];", "rhs[3 * fid[(a + 1) % n] + i] += R[3 * a + i];"),
     "lumped_mass_ignores_jacobian": ("M[fid[a]] += w[q] * d * N[a];", "M[fid[a]] += w[q] * N[a];"),
     "viscosity_ignores_eddy": ("if (terms & TERM_SGS) visc += nut;", "if (terms & TERM_SGS) visc += 0.5 * nut;"),
+    "laplacian_untransposed_inverse": ("s += Ki[j][i] * dN[3 * a + j];", "s += Ki[i][j] * dN[3 * a + j];"),
+    "laplacian_drops_jacobian": ("K[a * n + b] += w[q] * det * s;", "K[a * n + b] += w[q] * s;"),
+    "divergence_untransposed_inverse": ("div += ue[3 * a + i] * Ki[j][i] * dN[3 * a + j];",
+                                        "div += ue[3 * a + i] * Ki[i][j] * dN[3 * a + j];"),
 }
 
 
