@@ -85,7 +85,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--scatter", choices=["atomic", "colour"], default="atomic")
+    ap.add_argument("--scatter", choices=["chunk", "colour", "direct"], default="chunk")
+    ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -99,8 +100,10 @@ def main():
 
     case = meshgen.hybrid_2m_case()
     m = case.mesh
-    mesh = lesasm.Mesh.from_arrays(m, case.vreman_c, colour=(args.scatter == "colour"))
+    mesh = lesasm.Mesh.from_arrays(m, case.vreman_c, scatter=args.scatter)
     mesh.precision = args.precision
+    if args.chunk:
+        mesh.set_option(lesasm.OPT_CHUNK, args.chunk)
     u = mesh.to_internal(torch.from_numpy(case.u).cuda())
     p = mesh.to_internal(torch.from_numpy(case.p).cuda())
     rhs = torch.empty_like(u)

@@ -37,6 +37,77 @@ __global__ __launch_bounds__(256) void k_assemble(CatView c, const double *__res
         }
 }
 
+// Chunked variant: one workgroup per chunk of consecutive elements.  The
+// chunk's distinct nodes are loaded once into LDS (coordinates, velocity,
+// pressure), every element reads them from there, and element residuals are
+// summed into per-node LDS accumulators.  Afterwards each node is written once:
+// a plain store when every element touching it lies in this chunk (owned), an
+// FP64 device atomic otherwise.  LDS layout per chunk (doubles):
+//   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
+template <int T, typename R, bool HAS_P, bool PERIODIC>
+__global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const double *__restrict__ xyz,
+                                                        const double *__restrict__ u,
+                                                        const double *__restrict__ p, double nu, double cv,
+                                                        double *__restrict__ rhs) {
+    constexpr int nn = Ref<T>::nn;
+    extern __shared__ double lds[];
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    const int e0 = c.eoff[j], e1 = c.eoff[j + 1];
+    const int g0 = c.goff[j], ng = c.goff[j + 1] - g0;
+    const int f0 = PERIODIC ? c.foff[j] : g0;
+    const int nf = PERIODIC ? c.foff[j + 1] - f0 : ng;
+    double *sx = lds, *su = sx + 3 * ng, *sp = su + 3 * nf, *sacc = sp + nf;
+
+    for (int k = threadIdx.x; k < ng; k += blockDim.x) {
+        const size_t g = (size_t)c.gnodes[g0 + k];
+        sx[3 * k + 0] = xyz[3 * g + 0];
+        sx[3 * k + 1] = xyz[3 * g + 1];
+        sx[3 * k + 2] = xyz[3 * g + 2];
+    }
+    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+        const size_t f = (size_t)((uint32_t)c.fnodes[f0 + k] & ~kOwnedBit);
+        su[3 * k + 0] = u[3 * f + 0];
+        su[3 * k + 1] = u[3 * f + 1];
+        su[3 * k + 2] = u[3 * f + 2];
+        sp[k] = HAS_P ? p[f] : 0.0;
+        sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
+    }
+    __syncthreads();
+
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int lg[nn], lf[nn];
+#pragma unroll
+        for (int a = 0; a < nn; ++a) {
+            lg[a] = c.lg[(size_t)a * c.ld + e];
+            lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+        }
+        ElementData<T, R> d;
+        gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+        const double dl = c.delta[e];
+        R acc[nn][3];
+        element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)acc[a][i]);
+    }
+    __syncthreads();
+
+    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+        const uint32_t tag = (uint32_t)c.fnodes[f0 + k];
+        double *dst = rhs + 3 * (size_t)(tag & ~kOwnedBit);
+        if (tag & kOwnedBit) {
+            dst[0] = sacc[3 * k + 0];
+            dst[1] = sacc[3 * k + 1];
+            dst[2] = sacc[3 * k + 2];
+        } else {
+            unsafeAtomicAdd(dst + 0, sacc[3 * k + 0]);
+            unsafeAtomicAdd(dst + 1, sacc[3 * k + 1]);
+            unsafeAtomicAdd(dst + 2, sacc[3 * k + 2]);
+        }
+    }
+}
+
 __global__ void k_fill(double *__restrict__ a, size_t n, double v) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         a[i] = v;
@@ -84,6 +155,32 @@ static void dispatch_scatter(const CatView &v, bool atomic, bool has_p, int bloc
     }
 }
 
+template <int T, typename R>
+static void launch_chunks(const Category &c, bool has_p, bool periodic, int block, hipStream_t s,
+                          const double *xyz, const double *u, const double *p, double nu, double cv, double *rhs) {
+    ChunkView v{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_lg, c.d_lf, c.d_delta, (int32_t)c.n};
+    const size_t shm = sizeof(double) * (size_t)c.lds_doubles;
+    const dim3 grid(c.n_chunks), blk(block);
+    if (periodic) {
+        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, true>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, true>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+    } else {
+        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, false>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, false>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+    }
+}
+
+template <typename R>
+static void dispatch_chunks(const Category &c, bool has_p, bool periodic, int block, hipStream_t s,
+                            const double *xyz, const double *u, const double *p, double nu, double cv, double *rhs) {
+    switch (c.type) {
+    case LESASM_TET04: launch_chunks<LESASM_TET04, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    }
+}
+
 ProfileScope::ProfileScope(lesasm_mesh *m_, int slot_, hipStream_t s_) : m(m_), slot(slot_), s(s_) {
     if (!m->profile) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -113,9 +210,19 @@ static void dispatch_type(int type, const CatView &v, bool atomic, bool has_p, i
 // Launches every element kernel of one assembly on stream s (rhs already zeroed).
 int launch_assembly(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
     const bool atomic = !(m->flags & LESASM_MESH_SCATTER_COLOUR);
+    const bool chunked = !(m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT));
     for (int k = 0; k < kNumCat; ++k) {
         const Category &c = m->cat[k];
         if (c.n == 0) continue;
+        if (chunked) {
+            ProfileScope ps(m, LESASM_KERNEL_TET04 + k, s);
+            const bool periodic = c.d_lf != c.d_lg;
+            if (m->precision == LESASM_PREC_FP32)
+                dispatch_chunks<float>(c, p != nullptr, periodic, m->block, s, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else
+                dispatch_chunks<double>(c, p != nullptr, periodic, m->block, s, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            continue;
+        }
         const size_t nranges = atomic ? 1 : c.colour_off.size() - 1;
         for (size_t r = 0; r < nranges; ++r) {
             CatView v;

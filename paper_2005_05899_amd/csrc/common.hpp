@@ -56,7 +56,28 @@ struct Category {
     int32_t *d_cf = nullptr;          // field node ids, slot-major (aliases d_cg if identical)
     double *d_delta = nullptr;        // filter width per element
     std::vector<int64_t> colour_off;  // colour c = elements [colour_off[c], colour_off[c+1])
+    // chunked scatter: consecutive elements grouped so that their nodes fit in LDS
+    int32_t n_chunks = 0;
+    int32_t *d_eoff = nullptr;     // [n_chunks+1] element offsets within the category
+    int32_t *d_goff = nullptr;     // [n_chunks+1] offsets into d_gnodes
+    int32_t *d_gnodes = nullptr;   // geometry nodes of each chunk, ascending
+    int32_t *d_foff = nullptr;     // [n_chunks+1] offsets into d_fnodes (aliases d_goff without a field map)
+    int32_t *d_fnodes = nullptr;   // field nodes of each chunk; bit 31 set if the chunk owns the node
+    uint16_t *d_lg = nullptr;      // [nnode][n] chunk-local geometry index of each element slot
+    uint16_t *d_lf = nullptr;      // [nnode][n] chunk-local field index (aliases d_lg without a field map)
+    int lds_doubles = 0;           // largest LDS footprint of a chunk, in doubles
+    std::vector<int32_t> h_cg, h_cf;  // host copies of the internal connectivity (slot-major)
 };
+
+// Arguments of one chunked launch (one workgroup per chunk).
+struct ChunkView {
+    const int32_t *eoff, *goff, *gnodes, *foff, *fnodes;
+    const uint16_t *lg, *lf;
+    const double *delta;
+    int32_t ld;  // elements in the category
+};
+
+constexpr uint32_t kOwnedBit = 0x80000000u;
 
 // Arguments of one assembly launch over a contiguous element range of a category.
 struct CatView {
@@ -91,6 +112,8 @@ struct lesasm_mesh {
     int check_finite = 0;
     int block = 256;
     int profile = 0;
+    int chunk_elems = 512;          // elements per chunk of the chunked scatter
+    std::vector<int32_t> h_finc;    // incidences per internal field node (all types)
     // profiling: events pending per kernel slot, accumulated times and counts
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[LESASM_NUM_KERNEL_SLOTS];
     double prof_ms[LESASM_NUM_KERNEL_SLOTS] = {0};

@@ -64,6 +64,32 @@ __device__ __forceinline__ void gather(ElementData<T, R> &d, const CatView &c, i
     }
 }
 
+// Element data from chunk-staged LDS arrays: node coordinates sx[k][3] by
+// local geometry slot, velocity su[k][3] and pressure sp[k] by local field slot.
+template <int T, typename R, bool HAS_P>
+__device__ __forceinline__ void gather_lds(ElementData<T, R> &d, const int (&lg)[Ref<T>::nn],
+                                           const int (&lf)[Ref<T>::nn], const double *sx, const double *su,
+                                           const double *sp) {
+    constexpr int nn = Ref<T>::nn;
+    double x0[3], p0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        x0[k] = sx[3 * lg[0] + k];
+        d.u0[k] = su[3 * lf[0] + k];
+    }
+    if (HAS_P) p0 = sp[lf[0]];
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        d.fid[a] = lf[a];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            d.x[a][k] = a ? (R)(sx[3 * lg[a] + k] - x0[k]) : (R)0;
+            d.du[a][k] = a ? (R)(su[3 * lf[a] + k] - d.u0[k]) : (R)0;
+        }
+        d.dp[a] = (HAS_P && a) ? (R)(sp[lf[a]] - p0) : (R)0;
+    }
+}
+
 // Vreman: with alpha = G^T, beta = Delta^2 G G^T and alpha:alpha = tr(G G^T).
 // nu_t = c Delta^2 sqrt(B'/A) with B' the sum of the principal 2x2 minors of
 // G G^T (B_beta = Delta^4 B') and A its trace; 0 when A = 0; B' clamped at 0.
@@ -87,9 +113,85 @@ __device__ __forceinline__ R vreman_nut(const R G[3][3], R cd2) {
 // u_g = u0 + sum_a N_a du_a; nu_t; S = G + G^T; C = S u_g + tr(G) u_g;
 // f = w det (C + grad p); T = w (nu + nu_t) S adj^T  (= dV sigma J^-T);
 // acc[a] -= N_a f + T dN_a.
+// TET04 is affine: J, G, grad p and nu_t are constant over the element, and
+// the 4-point rule integrates N_a N_b exactly (degree 2), so its quadrature
+// sums collapse to closed forms of the same value:
+//   sum_g w_g N_a(g) = 1/24,   sum_g w_g N_a(g) N_b(g) = (1 + delta_ab) / 120.
+// With M = S + tr(G) I the EMAC term is C(u) = M u (linear in u), hence
+//   R_a = -det [ M (u_a + sum_b u_b) / 120 + grad p / 24 ] - T dN_a,
+//   T = (1/6) (nu + nu_t) S adj^T,  dN_0 = (-1,-1,-1), dN_a = e_(a-1).
+template <typename R, bool HAS_P>
+__device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> &d, R nu, R cd2, R acc[4][3]) {
+    R J[3][3], Gx[3][3], px[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            J[i][k] = d.x[k + 1][i];
+            Gx[i][k] = d.du[k + 1][i];
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) px[k] = HAS_P ? d.dp[k + 1] : (R)0;
+    R adj[3][3];
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+    const R rdet = (R)1 / det;
+    R G[3][3], q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            G[i][j] = (Gx[i][0] * adj[0][j] + Gx[i][1] * adj[1][j] + Gx[i][2] * adj[2][j]) * rdet;
+        q[i] = HAS_P ? (px[0] * adj[0][i] + px[1] * adj[1][i] + px[2] * adj[2][i]) * rdet : (R)0;
+    }
+    const R nut = vreman_nut<R>(G, cd2);
+    R S[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) S[i][j] = G[i][j] + G[j][i];
+    const R divu = G[0][0] + G[1][1] + G[2][2];
+    const R wvis = (R)(1.0 / 6.0) * (nu + nut);
+    R Tm[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Tm[i][k] = wvis * (S[i][0] * adj[k][0] + S[i][1] * adj[k][1] + S[i][2] * adj[k][2]);
+    // sum_b u_b = 4 u0 + sum_b du_b
+    R su[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) su[i] = (R)4 * (R)d.u0[i] + d.du[1][i] + d.du[2][i] + d.du[3][i];
+    const R c120 = det * (R)(1.0 / 120.0), c24 = det * (R)(1.0 / 24.0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        R v[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] = (R)d.u0[i] + d.du[a][i] + su[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const R Cm = S[i][0] * v[0] + S[i][1] * v[1] + S[i][2] * v[2] + divu * v[i];
+            const R visc = a ? Tm[i][a - 1] : -(Tm[i][0] + Tm[i][1] + Tm[i][2]);
+            acc[a][i] = -(c120 * Cm + c24 * q[i] + visc);
+        }
+    }
+}
+
 template <int T, typename R, bool HAS_P>
 __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R nu, R cd2,
                                                  R acc[Ref<T>::nn][3]) {
+    if constexpr (T == LESASM_TET04) {
+        tet_residual<R, HAS_P>(d, nu, cd2, acc);
+        return;
+    }
     using E = Ref<T>;
     constexpr int nn = E::nn;
     const auto &tab = RefConst<T>::tab();

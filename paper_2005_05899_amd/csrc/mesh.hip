@@ -175,6 +175,111 @@ static std::vector<int> greedy_colour(const std::vector<int64_t> &order, const i
     return col;
 }
 
+template <class T> static void dfree(lesasm_mesh *m, T *&p) {
+    if (!p) return;
+    auto it = std::find(m->allocs.begin(), m->allocs.end(), (void *)p);
+    if (it != m->allocs.end()) {
+        (void)hipFree(p);
+        m->allocs.erase(it);
+    }
+    p = nullptr;
+}
+
+// Chunks for the chunked scatter of category k: runs of consecutive internal
+// elements, at most m->chunk_elems long and with at most kChunkMaxNodes
+// distinct geometry and field nodes, so a chunk's node data fits in LDS.  Node
+// lists are sorted ascending (coalesced loads); a field node is owned by a
+// chunk when all of its incidences in the mesh lie in that chunk.
+constexpr int kChunkMaxNodes = 800;
+
+static int build_chunks(lesasm_mesh *m, int k) {
+    Category &c = m->cat[k];
+    dfree(m, c.d_eoff);
+    dfree(m, c.d_goff);
+    dfree(m, c.d_gnodes);
+    if (c.d_foff != c.d_goff) dfree(m, c.d_foff);
+    c.d_foff = nullptr;
+    dfree(m, c.d_fnodes);
+    if (c.d_lf != c.d_lg) dfree(m, c.d_lf);
+    c.d_lf = nullptr;
+    dfree(m, c.d_lg);
+    c.n_chunks = 0;
+    c.lds_doubles = 0;
+    if (c.n == 0) return LESASM_OK;
+    const bool periodic = !c.h_cf.empty();
+    const std::vector<int32_t> &cg = c.h_cg, &cf = periodic ? c.h_cf : c.h_cg;
+    const int nnode = c.type;
+    const int64_t n = c.n;
+    std::vector<int32_t> eoff{0}, goff{0}, foff{0}, gnodes, fnodes;
+    std::vector<uint16_t> lg((size_t)nnode * n), lf(periodic ? (size_t)nnode * n : 0);
+    std::vector<int32_t> gslot(m->n_nodes, -1), fslot(m->n_field, -1), fcount(m->n_field, 0);
+    std::vector<int32_t> gl, fl;
+    int64_t start = 0;
+    while (start < n) {
+        gl.clear();
+        fl.clear();
+        int64_t e = start;
+        while (e < n && e - start < m->chunk_elems) {
+            int newg = 0, newf = 0;
+            for (int a = 0; a < nnode; ++a) {
+                newg += gslot[cg[(size_t)a * n + e]] < 0;
+                newf += fslot[cf[(size_t)a * n + e]] < 0;
+            }
+            if (e > start && ((int)gl.size() + newg > kChunkMaxNodes || (int)fl.size() + newf > kChunkMaxNodes)) break;
+            for (int a = 0; a < nnode; ++a) {
+                const int32_t g = cg[(size_t)a * n + e], f = cf[(size_t)a * n + e];
+                if (gslot[g] < 0) { gslot[g] = 0; gl.push_back(g); }
+                if (fslot[f] < 0) { fslot[f] = 0; fl.push_back(f); }
+                fcount[f]++;
+            }
+            ++e;
+        }
+        std::sort(gl.begin(), gl.end());
+        std::sort(fl.begin(), fl.end());
+        for (size_t q = 0; q < gl.size(); ++q) gslot[gl[q]] = (int32_t)q;
+        for (size_t q = 0; q < fl.size(); ++q) fslot[fl[q]] = (int32_t)q;
+        for (int64_t x = start; x < e; ++x)
+            for (int a = 0; a < nnode; ++a) {
+                const size_t s = (size_t)a * n + x;
+                if (periodic) {
+                    lg[s] = (uint16_t)gslot[cg[s]];
+                    lf[s] = (uint16_t)fslot[cf[s]];
+                } else {
+                    lg[s] = (uint16_t)gslot[cg[s]];
+                }
+            }
+        for (int32_t g : gl) {
+            gnodes.push_back(g);
+            gslot[g] = -1;
+        }
+        for (int32_t f : fl) {
+            fnodes.push_back((int32_t)((uint32_t)f | (fcount[f] == m->h_finc[f] ? kOwnedBit : 0u)));
+            fcount[f] = 0;
+            fslot[f] = -1;
+        }
+        c.lds_doubles = std::max(c.lds_doubles, (int)(3 * gl.size() + 7 * fl.size()));
+        eoff.push_back((int32_t)e);
+        goff.push_back((int32_t)gnodes.size());
+        foff.push_back((int32_t)fnodes.size());
+        start = e;
+    }
+    c.n_chunks = (int32_t)(eoff.size() - 1);
+    int st;
+    if ((st = upload(m, &c.d_eoff, eoff))) return st;
+    if ((st = upload(m, &c.d_goff, goff))) return st;
+    if ((st = upload(m, &c.d_gnodes, gnodes))) return st;
+    if ((st = upload(m, &c.d_fnodes, fnodes))) return st;
+    if ((st = upload(m, &c.d_lg, lg))) return st;
+    if (periodic) {
+        if ((st = upload(m, &c.d_foff, foff))) return st;
+        if ((st = upload(m, &c.d_lf, lf))) return st;
+    } else {
+        c.d_foff = c.d_goff;
+        c.d_lf = c.d_lg;
+    }
+    return LESASM_OK;
+}
+
 }  // namespace lesasm
 
 using namespace lesasm;
@@ -193,8 +298,10 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
     if (ne > 0 && (!d->types || !d->conn_offsets || !d->conn))
         return fail(LESASM_E_INVALID_ARG, "mesh_create: types, conn_offsets or conn is NULL");
     if (nn > 0 && !d->coords) return fail(LESASM_E_INVALID_ARG, "mesh_create: coords is NULL");
-    if (d->flags & ~(LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_KEEP_ORDER))
+    if (d->flags & ~(LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_KEEP_ORDER | LESASM_MESH_SCATTER_DIRECT))
         return fail(LESASM_E_INVALID_ARG, "mesh_create: unknown flag bits");
+    if ((d->flags & LESASM_MESH_SCATTER_COLOUR) && (d->flags & LESASM_MESH_SCATTER_DIRECT))
+        return fail(LESASM_E_INVALID_ARG, "mesh_create: choose one scatter mode");
     if (!(d->vreman_c >= 0.0)) return fail(LESASM_E_INVALID_ARG, "mesh_create: vreman_c must be >= 0");
     const int32_t *fmap = d->field_node;
     const int64_t nf = fmap ? d->n_field_nodes : nn;
@@ -342,7 +449,18 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
         else if ((st = upload(m, &c.d_cf, cf)))
             return st;
         c.d_delta = m->d_delta + c.first;
+        c.h_cg.swap(cg);
+        c.h_cf.swap(cf);
     }
+    m->h_finc.assign(nf, 0);
+    for (int k = 0; k < kNumCat; ++k) {
+        const Category &c = m->cat[k];
+        const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
+        for (int32_t f : cf) m->h_finc[f]++;
+    }
+    if (!(d->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT)))
+        for (int k = 0; k < kNumCat; ++k)
+            if ((st = build_chunks(m, k))) return st;
 
     // geometry: det J check, Delta_e, lumped mass
     if (nf > 0) LESASM_HIP_TRY(hipMemset(m->d_mass, 0, sizeof(double) * nf));
@@ -470,6 +588,21 @@ extern "C" int lesasm_mesh_set_option(lesasm_mesh *m, int option, int64_t value)
     case LESASM_OPT_PROFILE:
         m->profile = value != 0;
         return LESASM_OK;
+    case LESASM_OPT_CHUNK: {
+        if (value < 32 || value > 4096) return fail(LESASM_E_UNSUPPORTED, "set_option: chunk must be in 32..4096");
+        if (m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT))
+            return fail(LESASM_E_STATE, "set_option: chunk size applies to the chunked scatter only");
+        int cur = 0;
+        LESASM_HIP_TRY(hipGetDevice(&cur));
+        if (cur != m->device) return fail(LESASM_E_STATE, "set_option: current device differs from the mesh's device");
+        LESASM_HIP_TRY(hipDeviceSynchronize());
+        m->chunk_elems = (int)value;
+        for (int k = 0; k < kNumCat; ++k) {
+            int st = build_chunks(m, k);
+            if (st) return st;
+        }
+        return LESASM_OK;
+    }
     default:
         return fail(LESASM_E_INVALID_ARG, "set_option: unknown option " + std::to_string(option));
     }
@@ -483,6 +616,7 @@ extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t 
     case LESASM_OPT_CHECK_FINITE: *value = m->check_finite; return LESASM_OK;
     case LESASM_OPT_BLOCK: *value = m->block; return LESASM_OK;
     case LESASM_OPT_PROFILE: *value = m->profile; return LESASM_OK;
+    case LESASM_OPT_CHUNK: *value = m->chunk_elems; return LESASM_OK;
     default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
     }
 }

@@ -42,9 +42,13 @@ def assert_close(got, ref, tol, what=""):
     assert worst <= tol, (what, errs)
 
 
-def run_gpu(torch, case, colour=False, keep_order=False, precision="fp64", with_p=True, mesh=None):
+def run_gpu(torch, case, colour=False, keep_order=False, precision="fp64", with_p=True, mesh=None, scatter=None,
+            chunk=None):
     from paper_2005_05899_amd import lesasm
-    m = mesh or lesasm.Mesh.from_arrays(case.mesh, case.vreman_c, colour=colour, keep_order=keep_order)
+    m = mesh or lesasm.Mesh.from_arrays(case.mesh, case.vreman_c, colour=colour, keep_order=keep_order,
+                                        scatter=scatter)
+    if chunk is not None:
+        m.set_option(lesasm.OPT_CHUNK, chunk)
     m.precision = precision
     u = m.to_internal(torch.from_numpy(case.u).cuda())
     p = m.to_internal(torch.from_numpy(case.p).cuda()) if (with_p and case.p is not None) else None
@@ -67,21 +71,33 @@ def small():
     return c, oracle.assemble(c.mesh, c.u, c.p, c.nu, c.vreman_c)
 
 
-def test_periodic_cube_fp64(torch_cuda, periodic):
+@pytest.mark.parametrize("scatter", ["chunk", "colour", "direct"])
+def test_periodic_cube_fp64(torch_cuda, periodic, scatter):
     c, ref = periodic
-    got, m = run_gpu(torch_cuda, c)
-    assert_close(got, ref, TOL64, "periodic 16^3 HEX08 fp64 atomic")
+    got, m = run_gpu(torch_cuda, c, scatter=scatter)
+    assert_close(got, ref, TOL64, f"periodic 16^3 HEX08 fp64 {scatter}")
     m.close()
 
 
-@pytest.mark.parametrize("colour,keep", [(False, False), (True, False), (False, True), (True, True)])
-def test_small_hybrid_fp64(torch_cuda, small, colour, keep):
+@pytest.mark.parametrize("scatter", ["chunk", "colour", "direct"])
+@pytest.mark.parametrize("keep", [False, True])
+def test_small_hybrid_fp64(torch_cuda, small, scatter, keep):
     c, ref = small
-    got, m = run_gpu(torch_cuda, c, colour=colour, keep_order=keep)
-    assert_close(got, ref, TOL64, f"small hybrid ({c.mesh.n_elems} el) colour={colour} keep={keep}")
-    if colour:
+    got, m = run_gpu(torch_cuda, c, scatter=scatter, keep_order=keep)
+    assert_close(got, ref, TOL64, f"small hybrid ({c.mesh.n_elems} el) scatter={scatter} keep={keep}")
+    if scatter == "colour":
         assert all(v > 0 for t, v in m.n_colours.items() if m.n_per_type[t] > 0)
     m.close()
+
+
+@pytest.mark.parametrize("chunk", [32, 100, 4096])
+def test_chunk_sizes(torch_cuda, small, periodic, chunk):
+    """Many small chunks (ragged last chunks) and one chunk per type; the
+    periodic cube exercises separate geometry and field node lists."""
+    for c, ref in (small, periodic):
+        got, m = run_gpu(torch_cuda, c, chunk=chunk)
+        assert_close(got, ref, TOL64, f"{c.name} chunk={chunk}")
+        m.close()
 
 
 def test_small_hybrid_without_pressure(torch_cuda, small):
@@ -242,7 +258,7 @@ def test_hybrid_2m_fp64_full(torch_cuda, hybrid2m):
     configuration, every node compared with the oracle."""
     c, ref = hybrid2m
     got, m = run_gpu(torch_cuda, c)
-    assert_close(got, ref, TOL64, "2M hybrid fp64 atomic")
+    assert_close(got, ref, TOL64, "2M hybrid fp64 chunked scatter")
     m.close()
 
 
@@ -253,8 +269,9 @@ def test_hybrid_2m_fp32_full(torch_cuda, hybrid2m):
     m.close()
 
 
-def test_hybrid_2m_colour(torch_cuda, hybrid2m):
+@pytest.mark.parametrize("scatter", ["colour", "direct"])
+def test_hybrid_2m_other_scatters(torch_cuda, hybrid2m, scatter):
     c, ref = hybrid2m
-    got, m = run_gpu(torch_cuda, c, colour=True)
-    assert_close(got, ref, TOL64, "2M hybrid fp64 colour")
+    got, m = run_gpu(torch_cuda, c, scatter=scatter)
+    assert_close(got, ref, TOL64, f"2M hybrid fp64 {scatter}")
     m.close()
