@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--scatter", choices=["chunk", "colour", "direct"], default="chunk")
+    ap.add_argument("--scatter", choices=["staged", "chunk_atomic", "colour", "direct"], default="staged")
     ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

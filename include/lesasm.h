@@ -61,15 +61,17 @@ extern "C" {
 #define LESASM_HEX08 8
 
 /* ---- mesh creation flags ----------------------------------------------- */
-#define LESASM_MESH_SCATTER_ATOMIC 0u /* default: elements in chunks (one workgroup each) whose nodes
-                                         are staged in LDS; residuals summed in LDS, then nodes owned
-                                         by the chunk are stored and shared ones added with FP64
-                                         device atomics */
+#define LESASM_MESH_SCATTER_STAGED 0u /* default: elements in chunks (one workgroup each) whose nodes
+                                         are staged in LDS; residuals summed in LDS; nodes owned by
+                                         the chunk are stored, shared ones written to per-chunk
+                                         staging rows that a gather kernel sums (no global atomics) */
 #define LESASM_MESH_SCATTER_COLOUR 1u /* greedy element colouring; one launch per colour, plain
                                          read-modify-write scatter, bitwise reproducible */
 #define LESASM_MESH_KEEP_ORDER 2u     /* keep the user's element and node order within each type */
 #define LESASM_MESH_SCATTER_DIRECT 4u /* one FP64 device atomic per element node and component
                                          (no LDS staging); kept for comparison */
+#define LESASM_MESH_SCATTER_CHUNK_ATOMIC 8u /* chunks as in STAGED, shared nodes added with FP64
+                                               device atomics instead of staging rows */
 
 typedef struct lesasm_mesh lesasm_mesh;
 
@@ -152,8 +154,9 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
 #define LESASM_OPT_CHECK_FINITE 3 /* 1: scan u and p for NaN/Inf first (synchronises) */
 #define LESASM_OPT_BLOCK 4        /* threads per block of the assembly kernels: 64, 128 or 256 */
 #define LESASM_OPT_PROFILE 5      /* 1: record HIP events around every kernel launch */
-#define LESASM_OPT_CHUNK 6        /* elements per chunk of the chunked scatter, 32..4096 (default
-                                     512); setting it rebuilds the chunks (synchronises) */
+#define LESASM_OPT_CHUNK 6        /* elements per chunk of the chunked scatters, 32..4096, or 0
+                                     (default) for min(512, max(64, 2^floor(log2(n_type/1024)))) per
+                                     type; setting it rebuilds the chunks (synchronises) */
 
 #define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
 #define LESASM_PREC_FP32 1 /* element contractions in FP32 on origin- and mean-shifted
@@ -187,7 +190,8 @@ int lesasm_assemble_momentum_rhs(lesasm_mesh *mesh, const double *d_u, const dou
 #define LESASM_KERNEL_PEN06 3
 #define LESASM_KERNEL_HEX08 4
 #define LESASM_KERNEL_INCREMENT 5 /* dt M_L^-1 scaling */
-#define LESASM_NUM_KERNEL_SLOTS 6
+#define LESASM_KERNEL_GATHER 6    /* staged scatter: sums of the staging rows of shared nodes */
+#define LESASM_NUM_KERNEL_SLOTS 7
 
 /* Per-slot sums of kernel durations (milliseconds, from HIP events recorded on
  * the caller's stream while LESASM_OPT_PROFILE is 1) and launch counts since

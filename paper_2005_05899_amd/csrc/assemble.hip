@@ -7,6 +7,8 @@
 // per element category (type); in colour mode one launch per colour, so no two
 // threads of a launch touch the same node and the scatter is a plain
 // read-modify-write with a fixed summation order.
+#include <algorithm>
+
 #include "element.hpp"
 
 namespace lesasm {
@@ -42,9 +44,9 @@ __global__ __launch_bounds__(256) void k_assemble(CatView c, const double *__res
 // pressure), every element reads them from there, and element residuals are
 // summed into per-node LDS accumulators.  Afterwards each node is written once:
 // a plain store when every element touching it lies in this chunk (owned), an
-// FP64 device atomic otherwise.  LDS layout per chunk (doubles):
+// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
 //   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
-template <int T, typename R, bool HAS_P, bool PERIODIC>
+template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
 __global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const double *__restrict__ xyz,
                                                         const double *__restrict__ u,
                                                         const double *__restrict__ p, double nu, double cv,
@@ -100,12 +102,37 @@ __global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const doubl
             dst[0] = sacc[3 * k + 0];
             dst[1] = sacc[3 * k + 1];
             dst[2] = sacc[3 * k + 2];
+        } else if (STAGED) {
+            double *row = c.stage + 3 * (size_t)c.fslot[f0 + k];
+            row[0] = sacc[3 * k + 0];
+            row[1] = sacc[3 * k + 1];
+            row[2] = sacc[3 * k + 2];
         } else {
             unsafeAtomicAdd(dst + 0, sacc[3 * k + 0]);
             unsafeAtomicAdd(dst + 1, sacc[3 * k + 1]);
             unsafeAtomicAdd(dst + 2, sacc[3 * k + 2]);
         }
     }
+}
+
+// Staged scatter, second phase: every node owned by no chunk sums its staging
+// rows in a fixed order (deterministic) and stores the result.
+__global__ void k_gather_shared(const int32_t *__restrict__ gnode, const int32_t *__restrict__ goffs,
+                                const int32_t *__restrict__ gslots, const double *__restrict__ stage,
+                                double *__restrict__ rhs, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int q = goffs[i]; q < goffs[i + 1]; ++q) {
+        const double *row = stage + 3 * (size_t)gslots[q];
+        s0 += row[0];
+        s1 += row[1];
+        s2 += row[2];
+    }
+    double *dst = rhs + 3 * (size_t)gnode[i];
+    dst[0] = s0;
+    dst[1] = s1;
+    dst[2] = s2;
 }
 
 __global__ void k_fill(double *__restrict__ a, size_t n, double v) {
@@ -155,29 +182,31 @@ static void dispatch_scatter(const CatView &v, bool atomic, bool has_p, int bloc
     }
 }
 
-template <int T, typename R>
-static void launch_chunks(const Category &c, bool has_p, bool periodic, int block, hipStream_t s,
-                          const double *xyz, const double *u, const double *p, double nu, double cv, double *rhs) {
-    ChunkView v{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_lg, c.d_lf, c.d_delta, (int32_t)c.n};
-    const size_t shm = sizeof(double) * (size_t)c.lds_doubles;
-    const dim3 grid(c.n_chunks), blk(block);
+template <int T, typename R, bool STAGED>
+static void launch_chunks(const ChunkView &v, int n_chunks, size_t shm, bool has_p, bool periodic, int block,
+                          hipStream_t s, const double *xyz, const double *u, const double *p, double nu, double cv,
+                          double *rhs) {
+    const dim3 grid(n_chunks), blk(block);
     if (periodic) {
-        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, true>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
-        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, true>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, true, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, true, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
     } else {
-        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, false>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
-        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, false>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, false, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, false, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
     }
 }
 
-template <typename R>
-static void dispatch_chunks(const Category &c, bool has_p, bool periodic, int block, hipStream_t s,
+template <typename R, bool STAGED>
+static void dispatch_chunks(const Category &c, double *stage, bool has_p, bool periodic, int block, hipStream_t s,
                             const double *xyz, const double *u, const double *p, double nu, double cv, double *rhs) {
+    ChunkView v{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_fslot, c.d_lg, c.d_lf, c.d_delta, stage,
+                (int32_t)c.n};
+    const size_t shm = sizeof(double) * (size_t)c.lds_doubles;
     switch (c.type) {
-    case LESASM_TET04: launch_chunks<LESASM_TET04, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R>(c, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_TET04: launch_chunks<LESASM_TET04, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
     }
 }
 
@@ -208,21 +237,61 @@ static void dispatch_type(int type, const CatView &v, bool atomic, bool has_p, i
 }
 
 // Launches every element kernel of one assembly on stream s (rhs already zeroed).
-int launch_assembly(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
-    const bool atomic = !(m->flags & LESASM_MESH_SCATTER_COLOUR);
-    const bool chunked = !(m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT));
+bool mesh_is_chunked(const lesasm_mesh *m) {
+    return !(m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT));
+}
+
+bool mesh_is_staged(const lesasm_mesh *m) {
+    return mesh_is_chunked(m) && !(m->flags & LESASM_MESH_SCATTER_CHUNK_ATOMIC);
+}
+
+// Chunked scatters: the type kernels run concurrently, the first on the
+// caller's stream and the others on the mesh's side streams (fork and join
+// through events, so the sequence can be captured in a graph), followed by
+// the gather of staged rows on the caller's stream.
+static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
+    const bool staged = mesh_is_staged(m);
+    LESASM_HIP_TRY(hipEventRecord(m->ev_fork, s));
+    int used = 0;
     for (int k = 0; k < kNumCat; ++k) {
         const Category &c = m->cat[k];
         if (c.n == 0) continue;
-        if (chunked) {
-            ProfileScope ps(m, LESASM_KERNEL_TET04 + k, s);
-            const bool periodic = c.d_lf != c.d_lg;
-            if (m->precision == LESASM_PREC_FP32)
-                dispatch_chunks<float>(c, p != nullptr, periodic, m->block, s, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else
-                dispatch_chunks<double>(c, p != nullptr, periodic, m->block, s, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            continue;
+        hipStream_t sk = s;
+        if (used > 0) {
+            sk = m->side[(used - 1) % 3];
+            if (used <= 3) LESASM_HIP_TRY(hipStreamWaitEvent(sk, m->ev_fork, 0));
         }
+        ++used;
+        ProfileScope ps(m, LESASM_KERNEL_TET04 + k, sk);
+        const bool periodic = c.d_lf != c.d_lg;
+        const bool f32 = m->precision == LESASM_PREC_FP32;
+        if (staged) {
+            if (f32) dispatch_chunks<float, true>(c, m->d_stage, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else dispatch_chunks<double, true>(c, m->d_stage, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+        } else {
+            if (f32) dispatch_chunks<float, false>(c, nullptr, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else dispatch_chunks<double, false>(c, nullptr, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+        }
+    }
+    for (int i = 0; i < std::min(used - 1, 3); ++i) {
+        LESASM_HIP_TRY(hipEventRecord(m->ev_join[i], m->side[i]));
+        LESASM_HIP_TRY(hipStreamWaitEvent(s, m->ev_join[i], 0));
+    }
+    if (staged && m->n_gather > 0) {
+        ProfileScope ps(m, LESASM_KERNEL_GATHER, s);
+        hipLaunchKernelGGL(k_gather_shared, dim3((m->n_gather + 255) / 256), dim3(256), 0, s, m->d_gnode, m->d_goffs,
+                           m->d_gslots, m->d_stage, rhs, m->n_gather);
+    }
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+int launch_assembly(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
+    const bool atomic = !(m->flags & LESASM_MESH_SCATTER_COLOUR);
+    if (mesh_is_chunked(m)) return launch_chunked(m, u, p, nu, rhs, s);
+    for (int k = 0; k < kNumCat; ++k) {
+        const Category &c = m->cat[k];
+        if (c.n == 0) continue;
         const size_t nranges = atomic ? 1 : c.colour_off.size() - 1;
         for (size_t r = 0; r < nranges; ++r) {
             CatView v;
@@ -277,7 +346,7 @@ extern "C" int lesasm_assemble_momentum_rhs(lesasm_mesh *m, const double *d_u, c
         if (flag) return fail(LESASM_E_NONFINITE, "assemble: u or p holds NaN/Inf");
     }
 
-    {
+    if (!mesh_is_staged(m)) {  // the staged scatter writes every node exactly once
         ProfileScope ps(m, LESASM_KERNEL_FILL, s);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n3, 256)), dim3(256), 0, s, d_rhs, n3, 0.0);
     }

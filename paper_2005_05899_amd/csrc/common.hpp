@@ -65,16 +65,20 @@ struct Category {
     int32_t *d_fnodes = nullptr;   // field nodes of each chunk; bit 31 set if the chunk owns the node
     uint16_t *d_lg = nullptr;      // [nnode][n] chunk-local geometry index of each element slot
     uint16_t *d_lf = nullptr;      // [nnode][n] chunk-local field index (aliases d_lg without a field map)
+    int32_t *d_fslot = nullptr;    // per d_fnodes entry: staging slot of a shared node, -1 if owned
     int lds_doubles = 0;           // largest LDS footprint of a chunk, in doubles
+    int chunk_elems = 0;           // chunk length used for this category
     std::vector<int32_t> h_cg, h_cf;  // host copies of the internal connectivity (slot-major)
+    std::vector<int32_t> h_fnodes;    // host copy of d_fnodes
 };
 
 // Arguments of one chunked launch (one workgroup per chunk).
 struct ChunkView {
-    const int32_t *eoff, *goff, *gnodes, *foff, *fnodes;
+    const int32_t *eoff, *goff, *gnodes, *foff, *fnodes, *fslot;
     const uint16_t *lg, *lf;
     const double *delta;
-    int32_t ld;  // elements in the category
+    double *stage;  // staging rows [slot][3] for shared nodes
+    int32_t ld;     // elements in the category
 };
 
 constexpr uint32_t kOwnedBit = 0x80000000u;
@@ -112,8 +116,19 @@ struct lesasm_mesh {
     int check_finite = 0;
     int block = 256;
     int profile = 0;
-    int chunk_elems = 512;          // elements per chunk of the chunked scatter
+    int chunk_elems = 0;            // elements per chunk of the chunked scatter (0: per-type heuristic)
     std::vector<int32_t> h_finc;    // incidences per internal field node (all types)
+    // staged scatter: shared nodes get one staging row per chunk touching them;
+    // after the element kernels every non-owned node sums its rows (CSR below)
+    double *d_stage = nullptr;      // [n_slots][3]
+    int64_t n_slots = 0;
+    int32_t n_gather = 0;           // field nodes owned by no chunk
+    int32_t *d_gnode = nullptr;     // [n_gather] their ids
+    int32_t *d_goffs = nullptr;     // [n_gather+1] CSR offsets into d_gslots
+    int32_t *d_gslots = nullptr;    // staging rows, in (type, chunk) order
+    // side streams and events running the four type kernels concurrently
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     // profiling: events pending per kernel slot, accumulated times and counts
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[LESASM_NUM_KERNEL_SLOTS];
     double prof_ms[LESASM_NUM_KERNEL_SLOTS] = {0};

@@ -125,19 +125,22 @@ static uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit of 63
 
 static void free_mesh(lesasm_mesh *m) {
     if (!m) return;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
     for (auto &v : m->pending)
         for (auto &ev : v) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
         }
-    int cur = 0;
-    bool have = hipGetDevice(&cur) == hipSuccess;
-    if (!m->allocs.empty()) {
-        (void)hipSetDevice(m->device);
-        (void)hipDeviceSynchronize();
-        for (void *p : m->allocs) (void)hipFree(p);
-        if (have) (void)hipSetDevice(cur);
+    for (int i = 0; i < 3; ++i) {
+        if (m->side[i]) (void)hipStreamDestroy(m->side[i]);
+        if (m->ev_join[i]) (void)hipEventDestroy(m->ev_join[i]);
     }
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    for (void *p : m->allocs) (void)hipFree(p);
+    if (have) (void)hipSetDevice(cur);
     delete m;
 }
 
@@ -192,8 +195,17 @@ template <class T> static void dfree(lesasm_mesh *m, T *&p) {
 // chunk when all of its incidences in the mesh lie in that chunk.
 constexpr int kChunkMaxNodes = 800;
 
+static int chunk_length(const lesasm_mesh *m, int64_t n) {
+    if (m->chunk_elems) return m->chunk_elems;
+    int ce = 64;
+    while (ce < 512 && 2 * ce <= n / 1024) ce *= 2;
+    return ce;
+}
+
 static int build_chunks(lesasm_mesh *m, int k) {
     Category &c = m->cat[k];
+    dfree(m, c.d_fslot);
+    c.h_fnodes.clear();
     dfree(m, c.d_eoff);
     dfree(m, c.d_goff);
     dfree(m, c.d_gnodes);
@@ -210,6 +222,8 @@ static int build_chunks(lesasm_mesh *m, int k) {
     const std::vector<int32_t> &cg = c.h_cg, &cf = periodic ? c.h_cf : c.h_cg;
     const int nnode = c.type;
     const int64_t n = c.n;
+    const int ce = chunk_length(m, n);
+    c.chunk_elems = ce;
     std::vector<int32_t> eoff{0}, goff{0}, foff{0}, gnodes, fnodes;
     std::vector<uint16_t> lg((size_t)nnode * n), lf(periodic ? (size_t)nnode * n : 0);
     std::vector<int32_t> gslot(m->n_nodes, -1), fslot(m->n_field, -1), fcount(m->n_field, 0);
@@ -219,7 +233,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
         gl.clear();
         fl.clear();
         int64_t e = start;
-        while (e < n && e - start < m->chunk_elems) {
+        while (e < n && e - start < ce) {
             int newg = 0, newf = 0;
             for (int a = 0; a < nnode; ++a) {
                 newg += gslot[cg[(size_t)a * n + e]] < 0;
@@ -269,6 +283,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
     if ((st = upload(m, &c.d_goff, goff))) return st;
     if ((st = upload(m, &c.d_gnodes, gnodes))) return st;
     if ((st = upload(m, &c.d_fnodes, fnodes))) return st;
+    c.h_fnodes.swap(fnodes);
     if ((st = upload(m, &c.d_lg, lg))) return st;
     if (periodic) {
         if ((st = upload(m, &c.d_foff, foff))) return st;
@@ -276,6 +291,86 @@ static int build_chunks(lesasm_mesh *m, int k) {
     } else {
         c.d_foff = c.d_goff;
         c.d_lf = c.d_lg;
+    }
+    return LESASM_OK;
+}
+
+// Staging rows of the staged scatter: one per (chunk, shared node), numbered in
+// (type, chunk, node) order, plus the CSR that lets each node owned by no
+// chunk sum its rows in that fixed order.
+static int build_staging(lesasm_mesh *m) {
+    dfree(m, m->d_stage);
+    dfree(m, m->d_gnode);
+    dfree(m, m->d_goffs);
+    dfree(m, m->d_gslots);
+    m->n_slots = 0;
+    m->n_gather = 0;
+    std::vector<int32_t> owned(m->n_field, 0), count(m->n_field, 0);
+    std::vector<std::vector<int32_t>> fslot(kNumCat);
+    int64_t next = 0;
+    for (int k = 0; k < kNumCat; ++k) {
+        Category &c = m->cat[k];
+        dfree(m, c.d_fslot);
+        fslot[k].resize(c.h_fnodes.size());
+        for (size_t q = 0; q < c.h_fnodes.size(); ++q) {
+            const uint32_t tag = (uint32_t)c.h_fnodes[q];
+            const int32_t f = (int32_t)(tag & ~kOwnedBit);
+            if (tag & kOwnedBit) {
+                owned[f] = 1;
+                fslot[k][q] = -1;
+            } else {
+                fslot[k][q] = (int32_t)next++;
+                count[f]++;
+            }
+        }
+    }
+    if (next >= INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "mesh_create: too many staging rows");
+    std::vector<int32_t> gnode, goffs{0};
+    std::vector<int32_t> pos(m->n_field, -1);
+    for (int64_t f = 0; f < m->n_field; ++f)
+        if (!owned[f]) {
+            pos[f] = (int32_t)goffs.back();
+            gnode.push_back((int32_t)f);
+            goffs.push_back(goffs.back() + count[f]);
+        }
+    std::vector<int32_t> gslots(next);
+    for (int k = 0; k < kNumCat; ++k) {
+        const Category &c = m->cat[k];
+        for (size_t q = 0; q < c.h_fnodes.size(); ++q)
+            if (fslot[k][q] >= 0) {
+                const int32_t f = (int32_t)((uint32_t)c.h_fnodes[q] & ~kOwnedBit);
+                gslots[pos[f]++] = fslot[k][q];
+            }
+    }
+    m->n_slots = next;
+    m->n_gather = (int32_t)gnode.size();
+    int st;
+    if ((st = dalloc(m, &m->d_stage, 3 * (size_t)next))) return st;
+    if ((st = upload(m, &m->d_gnode, gnode))) return st;
+    if ((st = upload(m, &m->d_goffs, goffs))) return st;
+    if ((st = upload(m, &m->d_gslots, gslots))) return st;
+    for (int k = 0; k < kNumCat; ++k)
+        if ((st = upload(m, &m->cat[k].d_fslot, fslot[k]))) return st;
+    return LESASM_OK;
+}
+
+static bool is_chunked(const lesasm_mesh *m) {
+    return !(m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT));
+}
+
+static bool is_staged(const lesasm_mesh *m) { return is_chunked(m) && !(m->flags & LESASM_MESH_SCATTER_CHUNK_ATOMIC); }
+
+static int build_scatter(lesasm_mesh *m) {
+    int st;
+    for (int k = 0; k < kNumCat; ++k)
+        if ((st = build_chunks(m, k))) return st;
+    if (is_staged(m) && (st = build_staging(m))) return st;
+    if (!m->side[0]) {
+        for (int i = 0; i < 3; ++i) {
+            LESASM_HIP_TRY(hipStreamCreateWithFlags(&m->side[i], hipStreamNonBlocking));
+            LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming));
+        }
+        LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
     }
     return LESASM_OK;
 }
@@ -298,9 +393,10 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
     if (ne > 0 && (!d->types || !d->conn_offsets || !d->conn))
         return fail(LESASM_E_INVALID_ARG, "mesh_create: types, conn_offsets or conn is NULL");
     if (nn > 0 && !d->coords) return fail(LESASM_E_INVALID_ARG, "mesh_create: coords is NULL");
-    if (d->flags & ~(LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_KEEP_ORDER | LESASM_MESH_SCATTER_DIRECT))
+    const uint32_t scatter_bits = LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT | LESASM_MESH_SCATTER_CHUNK_ATOMIC;
+    if (d->flags & ~(scatter_bits | LESASM_MESH_KEEP_ORDER))
         return fail(LESASM_E_INVALID_ARG, "mesh_create: unknown flag bits");
-    if ((d->flags & LESASM_MESH_SCATTER_COLOUR) && (d->flags & LESASM_MESH_SCATTER_DIRECT))
+    if (__builtin_popcount(d->flags & scatter_bits) > 1)
         return fail(LESASM_E_INVALID_ARG, "mesh_create: choose one scatter mode");
     if (!(d->vreman_c >= 0.0)) return fail(LESASM_E_INVALID_ARG, "mesh_create: vreman_c must be >= 0");
     const int32_t *fmap = d->field_node;
@@ -458,9 +554,7 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
         const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
         for (int32_t f : cf) m->h_finc[f]++;
     }
-    if (!(d->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT)))
-        for (int k = 0; k < kNumCat; ++k)
-            if ((st = build_chunks(m, k))) return st;
+    if (is_chunked(m) && (st = build_scatter(m))) return st;
 
     // geometry: det J check, Delta_e, lumped mass
     if (nf > 0) LESASM_HIP_TRY(hipMemset(m->d_mass, 0, sizeof(double) * nf));
@@ -589,19 +683,15 @@ extern "C" int lesasm_mesh_set_option(lesasm_mesh *m, int option, int64_t value)
         m->profile = value != 0;
         return LESASM_OK;
     case LESASM_OPT_CHUNK: {
-        if (value < 32 || value > 4096) return fail(LESASM_E_UNSUPPORTED, "set_option: chunk must be in 32..4096");
-        if (m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT))
-            return fail(LESASM_E_STATE, "set_option: chunk size applies to the chunked scatter only");
+        if (value != 0 && (value < 32 || value > 4096))
+            return fail(LESASM_E_UNSUPPORTED, "set_option: chunk must be 0 or in 32..4096");
+        if (!is_chunked(m)) return fail(LESASM_E_STATE, "set_option: chunk size applies to the chunked scatters only");
         int cur = 0;
         LESASM_HIP_TRY(hipGetDevice(&cur));
         if (cur != m->device) return fail(LESASM_E_STATE, "set_option: current device differs from the mesh's device");
         LESASM_HIP_TRY(hipDeviceSynchronize());
         m->chunk_elems = (int)value;
-        for (int k = 0; k < kNumCat; ++k) {
-            int st = build_chunks(m, k);
-            if (st) return st;
-        }
-        return LESASM_OK;
+        return build_scatter(m);
     }
     default:
         return fail(LESASM_E_INVALID_ARG, "set_option: unknown option " + std::to_string(option));

@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "lib
 
 OK, E_INVALID_ARG, E_INVERTED_ELEMENT, E_OOM, E_HIP, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 TET04, PYR05, PEN06, HEX08 = 4, 5, 6, 8
-MESH_SCATTER_ATOMIC, MESH_SCATTER_COLOUR, MESH_KEEP_ORDER, MESH_SCATTER_DIRECT = 0, 1, 2, 4
+MESH_SCATTER_STAGED, MESH_SCATTER_COLOUR, MESH_KEEP_ORDER, MESH_SCATTER_DIRECT, MESH_SCATTER_CHUNK_ATOMIC = 0, 1, 2, 4, 8
 OPT_PRECISION, OPT_RHS_MODE, OPT_CHECK_FINITE, OPT_BLOCK, OPT_PROFILE, OPT_CHUNK = 1, 2, 3, 4, 5, 6
-KERNEL_SLOTS = ("fill", "tet04", "pyr05", "pen06", "hex08", "increment")
+KERNEL_SLOTS = ("fill", "tet04", "pyr05", "pen06", "hex08", "increment", "gather")
 PREC_FP64, PREC_FP32 = 0, 1
 RHS_RESIDUAL, RHS_INCREMENT = 0, 1
 
@@ -105,7 +105,7 @@ class Mesh:
     def __init__(self, coords, types, conn_offsets, conn, field_node=None, n_field_nodes=0,
                  vreman_c: float = 0.1, colour: bool = False, keep_order: bool = False,
                  scatter: str | None = None):
-        """scatter: "chunk" (default), "colour" or "direct"; colour=True is "colour"."""
+        """scatter: "staged" (default), "chunk_atomic", "colour" or "direct"; colour=True is "colour"."""
         lib = load()
         self._keep = [np.ascontiguousarray(coords, np.float64), np.ascontiguousarray(types, np.uint8),
                       np.ascontiguousarray(conn_offsets, np.int64), np.ascontiguousarray(conn, np.int32),
@@ -113,7 +113,7 @@ class Mesh:
         c, t, o, cn, fn = self._keep
         d = MeshDesc(len(c), c.ctypes.data, len(t), t.ctypes.data, o.ctypes.data, cn.ctypes.data,
                      None if fn is None else fn.ctypes.data, int(n_field_nodes) if fn is not None else 0,
-                     float(vreman_c), self._flags(scatter or ("colour" if colour else "chunk"), keep_order))
+                     float(vreman_c), self._flags(scatter or ("colour" if colour else "staged"), keep_order))
         h = ctypes.c_void_p()
         check(lib.lesasm_mesh_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -129,7 +129,8 @@ class Mesh:
 
     @staticmethod
     def _flags(scatter: str, keep_order: bool) -> int:
-        f = {"chunk": MESH_SCATTER_ATOMIC, "colour": MESH_SCATTER_COLOUR, "direct": MESH_SCATTER_DIRECT}[scatter]
+        f = {"staged": MESH_SCATTER_STAGED, "chunk_atomic": MESH_SCATTER_CHUNK_ATOMIC, "colour": MESH_SCATTER_COLOUR,
+             "direct": MESH_SCATTER_DIRECT}[scatter]
         return f | (MESH_KEEP_ORDER if keep_order else 0)
 
     @classmethod

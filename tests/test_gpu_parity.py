@@ -71,7 +71,7 @@ def small():
     return c, oracle.assemble(c.mesh, c.u, c.p, c.nu, c.vreman_c)
 
 
-@pytest.mark.parametrize("scatter", ["chunk", "colour", "direct"])
+@pytest.mark.parametrize("scatter", ["staged", "chunk_atomic", "colour", "direct"])
 def test_periodic_cube_fp64(torch_cuda, periodic, scatter):
     c, ref = periodic
     got, m = run_gpu(torch_cuda, c, scatter=scatter)
@@ -79,7 +79,7 @@ def test_periodic_cube_fp64(torch_cuda, periodic, scatter):
     m.close()
 
 
-@pytest.mark.parametrize("scatter", ["chunk", "colour", "direct"])
+@pytest.mark.parametrize("scatter", ["staged", "chunk_atomic", "colour", "direct"])
 @pytest.mark.parametrize("keep", [False, True])
 def test_small_hybrid_fp64(torch_cuda, small, scatter, keep):
     c, ref = small
@@ -90,14 +90,32 @@ def test_small_hybrid_fp64(torch_cuda, small, scatter, keep):
     m.close()
 
 
-@pytest.mark.parametrize("chunk", [32, 100, 4096])
-def test_chunk_sizes(torch_cuda, small, periodic, chunk):
-    """Many small chunks (ragged last chunks) and one chunk per type; the
-    periodic cube exercises separate geometry and field node lists."""
+@pytest.mark.parametrize("scatter", ["staged", "chunk_atomic"])
+@pytest.mark.parametrize("chunk", [32, 100, 4096, 0])
+def test_chunk_sizes(torch_cuda, small, periodic, chunk, scatter):
+    """Many small chunks (ragged last chunks), one chunk per type, and the
+    per-type default; the periodic cube exercises separate geometry and field
+    node lists."""
     for c, ref in (small, periodic):
-        got, m = run_gpu(torch_cuda, c, chunk=chunk)
-        assert_close(got, ref, TOL64, f"{c.name} chunk={chunk}")
+        got, m = run_gpu(torch_cuda, c, chunk=chunk, scatter=scatter)
+        assert_close(got, ref, TOL64, f"{c.name} {scatter} chunk={chunk}")
         m.close()
+
+
+def test_staged_scatter_overwrites_every_node(torch_cuda, small):
+    """No zero-fill in the staged scatter: every node is stored exactly once,
+    so a NaN-filled output buffer must come back fully overwritten."""
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    c, ref = small
+    m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+    u = m.to_internal(torch.from_numpy(c.u).cuda())
+    p = m.to_internal(torch.from_numpy(c.p).cuda())
+    out = torch.full_like(u, float("nan"))
+    got = m.to_user(m.assemble_momentum_rhs(u, p, c.nu, out=out)).cpu().numpy()
+    assert np.isfinite(got).all()
+    assert_close(got, ref, TOL64, "staged, NaN-filled output")
+    m.close()
 
 
 def test_small_hybrid_without_pressure(torch_cuda, small):
@@ -258,7 +276,7 @@ def test_hybrid_2m_fp64_full(torch_cuda, hybrid2m):
     configuration, every node compared with the oracle."""
     c, ref = hybrid2m
     got, m = run_gpu(torch_cuda, c)
-    assert_close(got, ref, TOL64, "2M hybrid fp64 chunked scatter")
+    assert_close(got, ref, TOL64, "2M hybrid fp64 staged scatter")
     m.close()
 
 
@@ -269,7 +287,7 @@ def test_hybrid_2m_fp32_full(torch_cuda, hybrid2m):
     m.close()
 
 
-@pytest.mark.parametrize("scatter", ["colour", "direct"])
+@pytest.mark.parametrize("scatter", ["chunk_atomic", "colour", "direct"])
 def test_hybrid_2m_other_scatters(torch_cuda, hybrid2m, scatter):
     c, ref = hybrid2m
     got, m = run_gpu(torch_cuda, c, scatter=scatter)
