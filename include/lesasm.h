@@ -155,7 +155,7 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
 #define LESASM_OPT_BLOCK 4        /* threads per block of the assembly kernels: 64, 128 or 256 */
 #define LESASM_OPT_PROFILE 5      /* 1: record HIP events around every kernel launch */
 #define LESASM_OPT_CHUNK 6        /* elements per chunk of the chunked scatters, 32..4096, or 0
-                                     (default) for min(512, max(64, 2^floor(log2(n_type/1024)))) per
+                                     (default) for min(512, max(64, 2^floor(log2(n_type/256)))) per
                                      type; setting it rebuilds the chunks (synchronises) */
 
 #define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
@@ -199,6 +199,102 @@ int lesasm_assemble_momentum_rhs(lesasm_mesh *mesh, const double *d_u, const dou
  * the recorded events (host synchronisation).  ms[] and launches[] are host
  * arrays of LESASM_NUM_KERNEL_SLOTS entries; reset != 0 clears the sums.     */
 int lesasm_mesh_kernel_times(lesasm_mesh *mesh, double *ms, int64_t *launches, int reset);
+
+/* ---- fractional-step support (Section 3.2, Algorithm 1) ----------------- */
+
+/* Nodal divergence (D u)_a = int N_a div u dV, d_out[n_field_nodes] overwritten
+ * (projection step of the fractional-step scheme).  Asynchronous. */
+int lesasm_divergence(lesasm_mesh *mesh, const double *d_u, double *d_out, void *stream);
+
+/* Nodal pressure gradient (G p)_a = int N_a grad p dV, d_out[n_field_nodes][3]
+ * overwritten.  Asynchronous. */
+int lesasm_gradient(lesasm_mesh *mesh, const double *d_p, double *d_out, void *stream);
+
+typedef struct lesasm_stepper lesasm_stepper;
+
+/* Time stepper of Algorithm 1 on a mesh (which must outlive it): assembles the
+ * Laplacian K_ab = int grad N_a . grad N_b dV once (CSR on the device), keeps
+ * work vectors, and runs per step three explicit Runge-Kutta stages (Heun's
+ * third-order tableau: c = (0, 1/3, 2/3), a21 = 1/3, a32 = 2/3,
+ * b = (1/4, 0, 3/4)) and one pressure solve by Jacobi-preconditioned CG to
+ * relative residual rtol (at most maxit iterations).  Synchronises. */
+int lesasm_stepper_create(lesasm_mesh *mesh, double nu, double dt, double rtol, int maxit, lesasm_stepper **out);
+int lesasm_stepper_destroy(lesasm_stepper *stepper);
+
+/* One time step, in place on device arrays in internal order:
+ *   u* = u^n + dt (k1/4 + 3 k3/4) with k_s = M_L^-1 rhs(u_s, p^n);
+ *   K dp = -(1/dt) D u* (right-hand side projected to zero mean, dp zero mean);
+ *   u^n+1 = u* - dt M_L^-1 G dp;  p^n+1 = p^n + dp.
+ * The CG convergence test reads the residual on the host every few
+ * iterations, so the call synchronises the stream. */
+int lesasm_stepper_step(lesasm_stepper *stepper, double *d_u, double *d_p, void *stream);
+
+/* The three explicit stages alone: d_ustar = u* for (d_u, d_p).  Asynchronous. */
+int lesasm_stepper_rk3_stages(lesasm_stepper *stepper, const double *d_u, const double *d_p, double *d_ustar,
+                              void *stream);
+
+/* Mean-zero solution of K x = b - mean(b) by Jacobi-PCG.  Synchronises. */
+int lesasm_pressure_solve(lesasm_stepper *stepper, const double *d_b, double *d_x, void *stream);
+
+/* CG iterations and relative residual of the last pressure solve. */
+int lesasm_stepper_stats(const lesasm_stepper *stepper, int *cg_iters, double *cg_rel_residual);
+
+/* Copy the assembled Laplacian to host arrays (rowptr[n_field_nodes+1],
+ * col[nnz], val[nnz], any of them may be NULL); *nnz receives the count. */
+int lesasm_stepper_laplacian(lesasm_stepper *stepper, int32_t *rowptr, int32_t *col, double *val, int64_t *nnz);
+
+/* ---- batches of mesh partitions ---------------------------------------- */
+
+typedef struct lesasm_batch lesasm_batch;
+
+#define LESASM_ORDER_MESH 0          /* work queue in mesh, type, chunk order */
+#define LESASM_ORDER_LARGEST_FIRST 1 /* chunks by decreasing cost (elements x Gauss points) */
+#define LESASM_ORDER_INTERLEAVED 2   /* round-robin over meshes */
+
+/* Group 1..64 non-periodic meshes with the staged scatter (the meshes must
+ * outlive the batch and live on the current device).  Work items are
+ * (mesh, type, chunk) triples in a device queue; one persistent launch of a
+ * grid of grid_per_cu workgroups per compute unit drains it (Section 3.4.3:
+ * packs of elements of one category, here pulled from a queue instead of one
+ * kernel per pack).  Synchronises. */
+int lesasm_batch_create(lesasm_mesh *const *meshes, int n, lesasm_batch **out);
+int lesasm_batch_destroy(lesasm_batch *batch);
+
+/* Chunk length (0 = each mesh's default), queue order and workgroups per
+ * compute unit; rebuilds chunks and the queue (synchronises). */
+int lesasm_batch_configure(lesasm_batch *batch, int chunk, int order, int grid_per_cu);
+int lesasm_batch_get_config(const lesasm_batch *batch, int *chunk, int *order, int *grid_per_cu, int *n_items);
+
+/* Residual assembly of every mesh: host arrays of n device pointers
+ * d_u[i] ([n_field_nodes_i][3]), d_p[i] (or d_p == NULL for none), nu[i],
+ * d_rhs[i] (overwritten).  Same semantics as lesasm_assemble_momentum_rhs per
+ * mesh (residual mode); all meshes use the first mesh's precision option.
+ * Asynchronous: one small set-up kernel, the persistent element kernel and
+ * one gather kernel. */
+int lesasm_batch_assemble(lesasm_batch *batch, const double *const *d_u, const double *const *d_p,
+                          const double *nu, double *const *d_rhs, void *stream);
+
+/* Autotuner: times the batched assembly for chunk lengths {128, 256, 512,
+ * 1024} x the three queue orders x {2, 4} workgroups per compute unit
+ * (median of `reps` runs after one warm-up) and keeps the fastest.  With a
+ * cache_path, a line "signature chunk order grid ms" is looked up first
+ * (signature = compute units and element counts per mesh and type) and
+ * appended after tuning.  *best_ms receives the time.  Synchronises. */
+int lesasm_batch_tune(lesasm_batch *batch, const double *const *d_u, const double *const *d_p, const double *nu,
+                      double *const *d_rhs, const char *cache_path, int reps, double *best_ms);
+
+/* Three explicit Runge-Kutta stages of every mesh, in place on d_u[i] with
+ * d_p[i] fixed (Heun's third-order tableau, no pressure projection):
+ * k1 = dt M^-1 rhs(u), u2 = u + k1/3, k2 = dt M^-1 rhs(u2), u3 = u + 2 k2/3,
+ * k3 = dt M^-1 rhs(u3), u <- u + k1/4 + 3 k3/4.
+ *   _graph captures the sequence on `stream` (must not be NULL) into a HIP
+ *   graph bound to these pointers; _launch replays it (one host call per
+ *   step); _eager runs the same sequence without a graph. */
+int lesasm_batch_rk3_graph(lesasm_batch *batch, double *const *d_u, const double *const *d_p, const double *nu,
+                           double dt, void *stream);
+int lesasm_batch_rk3_launch(lesasm_batch *batch, void *stream);
+int lesasm_batch_rk3_eager(lesasm_batch *batch, double *const *d_u, const double *const *d_p, const double *nu,
+                           double dt, void *stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *lesasm_last_error(void);

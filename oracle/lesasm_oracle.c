@@ -551,3 +551,45 @@ int oracle_divergence(int64_t n_nodes, const double *coords, int64_t n_elems, co
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Residual of a given subgrid stress                                       */
+/* ------------------------------------------------------------------------ */
+
+/* R[a*3 + i] = sum_g w_g det J_g dN_a/dx_j tau_g,ij for a symmetric stress
+ * given per Gauss point as tau[g*6 + c], c = (xx, yy, zz, xy, xz, yz).  This
+ * is the weak form of -div(tau) moved to the right-hand side (the natural
+ * boundary term dropped), i.e. the subgrid part of the residual for a closure
+ * that supplies tau directly (with Vreman, tau = -2 nu_t eps(u)).           */
+int oracle_element_stress_residual(int type, const double *x, const double *tau, double *R)
+{
+    double pts[3 * ORACLE_MAX_GAUSS], w[ORACLE_MAX_GAUSS];
+    double N[ORACLE_MAX_NODE], dN[3 * ORACLE_MAX_NODE], dNdx[3 * ORACLE_MAX_NODE];
+    const int n = oracle_nnode(type);
+    const int ng = oracle_gauss(type, pts, w);
+    if (n < 0 || ng < 0) return -1;
+    for (int k = 0; k < 3 * n; ++k) R[k] = 0.0;
+    for (int q = 0; q < ng; ++q) {
+        double J[3][3], K[3][3];
+        oracle_shape(type, pts + 3 * q, N, dN);
+        jacobian(n, x, dN, J);
+        const double det = det3(J);
+        if (!(det > 0.0)) return -2;
+        inv3(J, det, K);
+        for (int a = 0; a < n; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j) s += K[j][i] * dN[3 * a + j];
+                dNdx[3 * a + i] = s;
+            }
+        const double *t = tau + 6 * q;
+        const double T[3][3] = {{t[0], t[3], t[4]}, {t[3], t[1], t[5]}, {t[4], t[5], t[2]}};
+        for (int a = 0; a < n; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j) s += dNdx[3 * a + j] * T[i][j];
+                R[3 * a + i] += w[q] * det * s;
+            }
+    }
+    return 0;
+}

@@ -57,6 +57,7 @@ def load():
         lib.oracle_filter_width.argtypes = [i64, P, i64, P, P, P, P]
         lib.oracle_element_laplacian.argtypes = [i32, P, P]
         lib.oracle_divergence.argtypes = [i64, P, i64, P, P, P, P, i64, P, P]
+        lib.oracle_element_stress_residual.argtypes = [i32, P, P, P]
         lib.oracle_bad_element.restype = ctypes.c_longlong
         _lib = lib
         return lib
@@ -184,3 +185,12 @@ def divergence(mesh, u) -> np.ndarray:
     _check(load().oracle_divergence(len(coords), _p(coords), len(types), _p(types), _p(offs), _p(conn), _p(fn), nf,
                                     _p(u), _p(out)))
     return out
+
+
+def element_stress_residual(t: int, x, tau) -> np.ndarray:
+    """R[a, i] = int dN_a/dx_j tau_ij dV for tau given per Gauss point [g, 6]."""
+    x = _f64(x)
+    tau = _f64(tau, (ngauss(t), 6))
+    R = np.zeros((nnode(t), 3))
+    _check(load().oracle_element_stress_residual(t, _p(x), _p(tau), _p(R)))
+    return R

@@ -39,80 +39,14 @@ __global__ __launch_bounds__(256) void k_assemble(CatView c, const double *__res
         }
 }
 
-// Chunked variant: one workgroup per chunk of consecutive elements.  The
-// chunk's distinct nodes are loaded once into LDS (coordinates, velocity,
-// pressure), every element reads them from there, and element residuals are
-// summed into per-node LDS accumulators.  Afterwards each node is written once:
-// a plain store when every element touching it lies in this chunk (owned), an
-// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
-//   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
+// Chunked scatters: one workgroup per chunk (see chunk_body).
 template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
 __global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const double *__restrict__ xyz,
                                                         const double *__restrict__ u,
                                                         const double *__restrict__ p, double nu, double cv,
                                                         double *__restrict__ rhs) {
-    constexpr int nn = Ref<T>::nn;
     extern __shared__ double lds[];
-    const int j = xcd_block(blockIdx.x, gridDim.x);
-    const int e0 = c.eoff[j], e1 = c.eoff[j + 1];
-    const int g0 = c.goff[j], ng = c.goff[j + 1] - g0;
-    const int f0 = PERIODIC ? c.foff[j] : g0;
-    const int nf = PERIODIC ? c.foff[j + 1] - f0 : ng;
-    double *sx = lds, *su = sx + 3 * ng, *sp = su + 3 * nf, *sacc = sp + nf;
-
-    for (int k = threadIdx.x; k < ng; k += blockDim.x) {
-        const size_t g = (size_t)c.gnodes[g0 + k];
-        sx[3 * k + 0] = xyz[3 * g + 0];
-        sx[3 * k + 1] = xyz[3 * g + 1];
-        sx[3 * k + 2] = xyz[3 * g + 2];
-    }
-    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
-        const size_t f = (size_t)((uint32_t)c.fnodes[f0 + k] & ~kOwnedBit);
-        su[3 * k + 0] = u[3 * f + 0];
-        su[3 * k + 1] = u[3 * f + 1];
-        su[3 * k + 2] = u[3 * f + 2];
-        sp[k] = HAS_P ? p[f] : 0.0;
-        sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
-    }
-    __syncthreads();
-
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        int lg[nn], lf[nn];
-#pragma unroll
-        for (int a = 0; a < nn; ++a) {
-            lg[a] = c.lg[(size_t)a * c.ld + e];
-            lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
-        }
-        ElementData<T, R> d;
-        gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
-        const double dl = c.delta[e];
-        R acc[nn][3];
-        element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
-#pragma unroll
-        for (int a = 0; a < nn; ++a)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)acc[a][i]);
-    }
-    __syncthreads();
-
-    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
-        const uint32_t tag = (uint32_t)c.fnodes[f0 + k];
-        double *dst = rhs + 3 * (size_t)(tag & ~kOwnedBit);
-        if (tag & kOwnedBit) {
-            dst[0] = sacc[3 * k + 0];
-            dst[1] = sacc[3 * k + 1];
-            dst[2] = sacc[3 * k + 2];
-        } else if (STAGED) {
-            double *row = c.stage + 3 * (size_t)c.fslot[f0 + k];
-            row[0] = sacc[3 * k + 0];
-            row[1] = sacc[3 * k + 1];
-            row[2] = sacc[3 * k + 2];
-        } else {
-            unsafeAtomicAdd(dst + 0, sacc[3 * k + 0]);
-            unsafeAtomicAdd(dst + 1, sacc[3 * k + 1]);
-            unsafeAtomicAdd(dst + 2, sacc[3 * k + 2]);
-        }
-    }
+    chunk_body<T, R, HAS_P, PERIODIC, STAGED>(c, xcd_block(blockIdx.x, gridDim.x), lds, xyz, u, p, nu, cv, rhs);
 }
 
 // Staged scatter, second phase: every node owned by no chunk sums its staging
@@ -313,6 +247,27 @@ int launch_assembly(lesasm_mesh *m, const double *u, const double *p, double nu,
     return LESASM_OK;
 }
 
+// One assembly on stream s after argument checks: zero-fill (unless staged),
+// element kernels, optional dt M_L^-1 scaling.
+int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, double dt, double *rhs, hipStream_t s,
+                  bool increment) {
+    if (m->n_field == 0) return LESASM_OK;
+    const size_t n3 = 3 * (size_t)m->n_field;
+    if (!mesh_is_staged(m)) {  // the staged scatter writes every node exactly once
+        ProfileScope ps(m, LESASM_KERNEL_FILL, s);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n3, 256)), dim3(256), 0, s, rhs, n3, 0.0);
+    }
+    int st = launch_assembly(m, u, p, nu, rhs, s);
+    if (st) return st;
+    if (increment) {
+        ProfileScope ps(m, LESASM_KERNEL_INCREMENT, s);
+        hipLaunchKernelGGL(k_increment, dim3(grid_for(m->n_field, 256)), dim3(256), 0, s, rhs, m->d_mass, dt,
+                           (size_t)m->n_field);
+    }
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
 }  // namespace lesasm
 
 using namespace lesasm;
@@ -346,19 +301,7 @@ extern "C" int lesasm_assemble_momentum_rhs(lesasm_mesh *m, const double *d_u, c
         if (flag) return fail(LESASM_E_NONFINITE, "assemble: u or p holds NaN/Inf");
     }
 
-    if (!mesh_is_staged(m)) {  // the staged scatter writes every node exactly once
-        ProfileScope ps(m, LESASM_KERNEL_FILL, s);
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(n3, 256)), dim3(256), 0, s, d_rhs, n3, 0.0);
-    }
-    int st = launch_assembly(m, d_u, d_p, nu, d_rhs, s);
-    if (st) return st;
-    if (m->rhs_mode == LESASM_RHS_INCREMENT) {
-        ProfileScope ps(m, LESASM_KERNEL_INCREMENT, s);
-        hipLaunchKernelGGL(k_increment, dim3(grid_for(m->n_field, 256)), dim3(256), 0, s, d_rhs, m->d_mass, dt,
-                           (size_t)m->n_field);
-    }
-    LESASM_HIP_TRY(hipGetLastError());
-    return LESASM_OK;
+    return assemble_into(m, d_u, d_p, nu, dt, d_rhs, s, m->rhs_mode == LESASM_RHS_INCREMENT);
 }
 
 extern "C" int lesasm_mesh_kernel_times(lesasm_mesh *m, double *ms, int64_t *launches, int reset) {

@@ -1,0 +1,621 @@
+// Batched assembly of many mesh partitions in one persistent launch.
+//
+// The paper packs elements of one category into large packs and runs one
+// kernel per pack on several streams (Section 3.4.3 and Section 5: pack size,
+// threads per block and the number of streams tuned by hand).  Here every
+// (mesh, element type, chunk) triple of a batch is one item of a device work
+// queue; a grid sized to fill the GPU pulls items with an atomic counter until
+// the queue is empty, so uneven partitions need no per-mesh launches.  Chunk
+// length and queue order are set by an autotuner.  A three-stage Runge-Kutta
+// update of all meshes can be captured into a HIP graph and replayed with one
+// host call.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <numeric>
+#include <sstream>
+
+#include "element.hpp"
+
+namespace lesasm {
+
+constexpr int kMaxBatch = 64;
+
+// Static description of one (mesh, type) pair.
+struct BatchEntry {
+    ChunkView v;           // chunk arrays of the type (stage pointer = the mesh's staging rows)
+    const double *xyz;
+    double cv;             // Vreman constant
+    int type;
+    int mesh;
+};
+
+// Per-call pointers of every mesh (written on the device by k_batch_begin).
+struct BatchCall {
+    const double *u[kMaxBatch];
+    const double *p[kMaxBatch];
+    double *rhs[kMaxBatch];
+    double nu[kMaxBatch];
+};
+
+// Per-mesh arrays for the gather and update kernels.
+struct BatchMeshDev {
+    const int32_t *gnode, *goffs, *gslots;
+    const double *stage, *mass;
+};
+
+__global__ void k_batch_begin(BatchCall args, BatchCall *dst, int *head) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *dst = args;
+        *head = 0;
+    }
+}
+
+template <typename R, bool HAS_P>
+__device__ __forceinline__ void batch_item(const BatchEntry &be, const BatchCall *call, int chunk, double *lds) {
+    const int mi = be.mesh;
+    const double *u = call->u[mi];
+    const double *p = HAS_P ? call->p[mi] : nullptr;
+    double *rhs = call->rhs[mi];
+    const double nu = call->nu[mi];
+    switch (be.type) {
+    case LESASM_TET04: chunk_body<LESASM_TET04, R, HAS_P, false, true>(be.v, chunk, lds, be.xyz, u, p, nu, be.cv, rhs); break;
+    case LESASM_PYR05: chunk_body<LESASM_PYR05, R, HAS_P, false, true>(be.v, chunk, lds, be.xyz, u, p, nu, be.cv, rhs); break;
+    case LESASM_PEN06: chunk_body<LESASM_PEN06, R, HAS_P, false, true>(be.v, chunk, lds, be.xyz, u, p, nu, be.cv, rhs); break;
+    case LESASM_HEX08: chunk_body<LESASM_HEX08, R, HAS_P, false, true>(be.v, chunk, lds, be.xyz, u, p, nu, be.cv, rhs); break;
+    }
+}
+
+// Persistent element kernel: each workgroup takes queue items until the
+// counter passes the end of the queue (every workgroup reaches that exit).
+template <typename R, bool HAS_P>
+__global__ __launch_bounds__(256) void k_batch_assemble(const BatchEntry *__restrict__ entries,
+                                                        const BatchCall *__restrict__ call,
+                                                        const int32_t *__restrict__ wentry,
+                                                        const int32_t *__restrict__ wchunk, int nwork, int *head) {
+    extern __shared__ double lds[];
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = atomicAdd(head, 1);
+        __syncthreads();
+        const int w = item;
+        __syncthreads();
+        if (w >= nwork) return;
+        batch_item<R, HAS_P>(entries[wentry[w]], call, wchunk[w], lds);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int find_mesh(const int64_t *prefix, int n, int64_t i) {
+    int lo = 0, hi = n;  // largest m with prefix[m] <= i
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Shared nodes of every mesh: sum of staging rows (fixed order).
+__global__ void k_batch_gather(const BatchMeshDev *__restrict__ md, const BatchCall *__restrict__ call,
+                               const int64_t *__restrict__ gprefix, int nmesh) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= gprefix[nmesh]) return;
+    const int mi = find_mesh(gprefix, nmesh, i);
+    const BatchMeshDev &d = md[mi];
+    const int k = (int)(i - gprefix[mi]);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int q = d.goffs[k]; q < d.goffs[k + 1]; ++q) {
+        const double *row = d.stage + 3 * (size_t)d.gslots[q];
+        s0 += row[0];
+        s1 += row[1];
+        s2 += row[2];
+    }
+    double *dst = call->rhs[mi] + 3 * (size_t)d.gnode[k];
+    dst[0] = s0;
+    dst[1] = s1;
+    dst[2] = s2;
+}
+
+// Runge-Kutta update over all meshes' nodes (node ranges by prefix):
+//   kout = dt M^-1 rhs (in place in rhs), then y = base + a1 k1 + a2 kout.
+struct UpdateArgs {
+    const double *base[kMaxBatch];
+    double *rhs[kMaxBatch];  // stage residual, scaled in place to dt M^-1 rhs
+    const double *k1[kMaxBatch];
+    double *y[kMaxBatch];
+    double a1, a2, dt;
+};
+
+__global__ void k_batch_update(UpdateArgs a, const BatchMeshDev *__restrict__ md, const int64_t *__restrict__ nprefix,
+                               int nmesh) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nprefix[nmesh]) return;
+    const int mi = find_mesh(nprefix, nmesh, i);
+    const size_t k = (size_t)(i - nprefix[mi]);
+    const double s = a.dt / md[mi].mass[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double kv = s * a.rhs[mi][3 * k + c];
+        a.rhs[mi][3 * k + c] = kv;
+        double v = a.base[mi][3 * k + c] + a.a2 * kv;
+        if (a.k1[mi]) v += a.a1 * a.k1[mi][3 * k + c];
+        a.y[mi][3 * k + c] = v;
+    }
+}
+
+}  // namespace lesasm
+
+using namespace lesasm;
+
+struct lesasm_batch {
+    int device = 0;
+    std::vector<lesasm_mesh *> meshes;
+    int chunk = 0;   // 0: each mesh's own default
+    int order = 0;   // LESASM_ORDER_*
+    int grid_per_cu = 2;
+    int n_cu = 256;
+    // device tables
+    BatchEntry *d_entries = nullptr;
+    BatchCall *d_call = nullptr;
+    BatchMeshDev *d_md = nullptr;
+    int64_t *d_gprefix = nullptr, *d_nprefix = nullptr;
+    int32_t *d_wentry = nullptr, *d_wchunk = nullptr;
+    int *d_head = nullptr;
+    int nwork = 0, lds_doubles = 0;
+    int64_t total_gather = 0, total_nodes = 0;
+    std::vector<void *> allocs;
+    // Runge-Kutta work arrays (one slab each, per-mesh offsets) and the graph
+    double *k1 = nullptr, *k3 = nullptr, *us = nullptr;
+    std::vector<int64_t> node_off;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_tune_ms = 0.0;
+};
+
+namespace {
+
+template <class T> int balloc(lesasm_batch *b, T **p, size_t n) {
+    *p = nullptr;
+    if (!n) return LESASM_OK;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LESASM_E_OOM, "batch: hipMalloc failed");
+    }
+    b->allocs.push_back(q);
+    *p = (T *)q;
+    return LESASM_OK;
+}
+
+template <class T> void bfree(lesasm_batch *b, T *&p) {
+    if (!p) return;
+    auto it = std::find(b->allocs.begin(), b->allocs.end(), (void *)p);
+    if (it != b->allocs.end()) {
+        (void)hipFree(p);
+        b->allocs.erase(it);
+    }
+    p = nullptr;
+}
+
+void batch_free(lesasm_batch *b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    for (void *p : b->allocs) (void)hipFree(p);
+    delete b;
+}
+
+// Work items ordered by the queue policy.  Cost of a chunk = elements x Gauss
+// points of its type (the paper's per-element weight is its number of Gauss
+// points).
+int build_work(lesasm_batch *b) {
+    struct Item {
+        int32_t entry, chunk;
+        int64_t cost;
+        int mesh;
+    };
+    std::vector<Item> items;
+    std::vector<BatchEntry> entries;
+    int lds = 0;
+    for (size_t mi = 0; mi < b->meshes.size(); ++mi) {
+        lesasm_mesh *m = b->meshes[mi];
+        for (int k = 0; k < kNumCat; ++k) {
+            Category &c = m->cat[k];
+            if (c.n == 0) continue;
+            std::vector<int32_t> eoff(c.n_chunks + 1);
+            LESASM_HIP_TRY(hipMemcpy(eoff.data(), c.d_eoff, sizeof(int32_t) * eoff.size(), hipMemcpyDeviceToHost));
+            const int ng = c.type == LESASM_TET04 ? 4 : (c.type == LESASM_PEN06 ? 6 : 8);
+            const int eid = (int)entries.size();
+            BatchEntry be;
+            be.v = ChunkView{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_fslot, c.d_lg, c.d_lf,
+                             c.d_delta, m->d_stage, (int32_t)c.n};
+            be.xyz = m->d_xyz;
+            be.cv = m->vreman_c;
+            be.type = c.type;
+            be.mesh = (int)mi;
+            entries.push_back(be);
+            lds = std::max(lds, c.lds_doubles);
+            for (int j = 0; j < c.n_chunks; ++j)
+                items.push_back({eid, j, (int64_t)(eoff[j + 1] - eoff[j]) * ng, (int)mi});
+        }
+    }
+    if (b->order == LESASM_ORDER_LARGEST_FIRST) {
+        std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    } else if (b->order == LESASM_ORDER_INTERLEAVED) {
+        // round-robin over meshes: the r-th chunk of every mesh, then the (r+1)-th ...
+        std::vector<std::vector<Item>> per(b->meshes.size());
+        for (const Item &it : items) per[it.mesh].push_back(it);
+        items.clear();
+        for (size_t r = 0;; ++r) {
+            bool any = false;
+            for (auto &v : per)
+                if (r < v.size()) {
+                    items.push_back(v[r]);
+                    any = true;
+                }
+            if (!any) break;
+        }
+    }
+    std::vector<int32_t> we(items.size()), wc(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+        we[i] = items[i].entry;
+        wc[i] = items[i].chunk;
+    }
+    bfree(b, b->d_entries);
+    bfree(b, b->d_wentry);
+    bfree(b, b->d_wchunk);
+    int st;
+    if ((st = balloc(b, &b->d_entries, entries.size())) || (st = balloc(b, &b->d_wentry, we.size())) ||
+        (st = balloc(b, &b->d_wchunk, wc.size())))
+        return st;
+    if (!entries.empty())
+        LESASM_HIP_TRY(hipMemcpy(b->d_entries, entries.data(), sizeof(BatchEntry) * entries.size(), hipMemcpyHostToDevice));
+    if (!we.empty()) {
+        LESASM_HIP_TRY(hipMemcpy(b->d_wentry, we.data(), sizeof(int32_t) * we.size(), hipMemcpyHostToDevice));
+        LESASM_HIP_TRY(hipMemcpy(b->d_wchunk, wc.data(), sizeof(int32_t) * wc.size(), hipMemcpyHostToDevice));
+    }
+    b->nwork = (int)items.size();
+    b->lds_doubles = lds;
+    return LESASM_OK;
+}
+
+int build_tables(lesasm_batch *b) {
+    const int n = (int)b->meshes.size();
+    std::vector<BatchMeshDev> md(n);
+    std::vector<int64_t> gp(n + 1, 0), np(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        lesasm_mesh *m = b->meshes[i];
+        md[i] = BatchMeshDev{m->d_gnode, m->d_goffs, m->d_gslots, m->d_stage, m->d_mass};
+        gp[i + 1] = gp[i] + m->n_gather;
+        np[i + 1] = np[i] + m->n_field;
+    }
+    b->total_gather = gp[n];
+    b->total_nodes = np[n];
+    b->node_off = np;
+    bfree(b, b->d_md);
+    bfree(b, b->d_gprefix);
+    bfree(b, b->d_nprefix);
+    int st;
+    if ((st = balloc(b, &b->d_md, (size_t)n)) || (st = balloc(b, &b->d_gprefix, (size_t)n + 1)) ||
+        (st = balloc(b, &b->d_nprefix, (size_t)n + 1)))
+        return st;
+    LESASM_HIP_TRY(hipMemcpy(b->d_md, md.data(), sizeof(BatchMeshDev) * n, hipMemcpyHostToDevice));
+    LESASM_HIP_TRY(hipMemcpy(b->d_gprefix, gp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    LESASM_HIP_TRY(hipMemcpy(b->d_nprefix, np.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    return LESASM_OK;
+}
+
+int rebuild(lesasm_batch *b) {
+    for (lesasm_mesh *m : b->meshes) {
+        int st = lesasm_mesh_set_option(m, LESASM_OPT_CHUNK, b->chunk);
+        if (st) return st;
+    }
+    int st;
+    if ((st = build_tables(b))) return st;
+    if ((st = build_work(b))) return st;
+    if (b->graph_exec) {  // chunk arrays moved: an instantiated graph is stale
+        (void)hipGraphExecDestroy(b->graph_exec);
+        (void)hipGraphDestroy(b->graph);
+        b->graph_exec = nullptr;
+        b->graph = nullptr;
+    }
+    return LESASM_OK;
+}
+
+// Launch of the whole batch assembly (begin, persistent kernel, gather) on s.
+int batch_launch(lesasm_batch *b, const BatchCall &call, bool has_p, bool fp32, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, call, b->d_call, b->d_head);
+    const int grid = std::max(1, std::min(b->nwork, b->n_cu * b->grid_per_cu));
+    const size_t shm = sizeof(double) * (size_t)b->lds_doubles;
+    if (b->nwork > 0) {
+        if (fp32) {
+            if (has_p) hipLaunchKernelGGL((k_batch_assemble<float, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
+            else hipLaunchKernelGGL((k_batch_assemble<float, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
+        } else {
+            if (has_p) hipLaunchKernelGGL((k_batch_assemble<double, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
+            else hipLaunchKernelGGL((k_batch_assemble<double, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
+        }
+    }
+    if (b->total_gather > 0)
+        hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((b->total_gather + 255) / 256)), dim3(256), 0, s, b->d_md,
+                           b->d_call, b->d_gprefix, (int)b->meshes.size());
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+int make_call(lesasm_batch *b, const double *const *u, const double *const *p, const double *nu,
+              double *const *rhs, BatchCall &call) {
+    std::memset(&call, 0, sizeof(call));
+    for (size_t i = 0; i < b->meshes.size(); ++i) {
+        if (!u[i] || !rhs[i]) return fail(LESASM_E_INVALID_ARG, "batch: NULL u or rhs pointer");
+        call.u[i] = u[i];
+        call.p[i] = p ? p[i] : nullptr;
+        call.rhs[i] = rhs[i];
+        call.nu[i] = nu[i];
+        if (p && !p[i]) return fail(LESASM_E_INVALID_ARG, "batch: p must be given for all meshes or none");
+    }
+    return LESASM_OK;
+}
+
+}  // namespace
+
+extern "C" int lesasm_batch_create(lesasm_mesh *const *meshes, int n, lesasm_batch **out) {
+    if (!out) return fail(LESASM_E_INVALID_ARG, "batch_create: out is NULL");
+    *out = nullptr;
+    if (!meshes || n < 1 || n > kMaxBatch)
+        return fail(LESASM_E_INVALID_ARG, "batch_create: need 1.." + std::to_string(kMaxBatch) + " meshes");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    for (int i = 0; i < n; ++i) {
+        const lesasm_mesh *m = meshes[i];
+        if (!m) return fail(LESASM_E_INVALID_ARG, "batch_create: NULL mesh");
+        if (m->device != dev) return fail(LESASM_E_STATE, "batch_create: meshes must live on the current device");
+        if (m->flags & (LESASM_MESH_SCATTER_COLOUR | LESASM_MESH_SCATTER_DIRECT | LESASM_MESH_SCATTER_CHUNK_ATOMIC))
+            return fail(LESASM_E_UNSUPPORTED, "batch_create: meshes must use the staged scatter");
+        for (int k = 0; k < kNumCat; ++k)
+            if (m->cat[k].d_lf != m->cat[k].d_lg)
+                return fail(LESASM_E_UNSUPPORTED, "batch_create: periodic meshes are not batched");
+        for (int j = 0; j < i; ++j)
+            if (meshes[j] == m) return fail(LESASM_E_INVALID_ARG, "batch_create: a mesh appears twice");
+    }
+    auto *b = new lesasm_batch();
+    struct Guard {
+        lesasm_batch *p;
+        ~Guard() { batch_free(p); }
+    } guard{b};
+    b->device = dev;
+    b->meshes.assign(meshes, meshes + n);
+    hipDeviceProp_t prop;
+    LESASM_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    b->n_cu = prop.multiProcessorCount;
+    int st;
+    if ((st = balloc(b, &b->d_call, 1)) || (st = balloc(b, &b->d_head, 1))) return st;
+    LESASM_HIP_TRY(hipEventCreate(&b->ev0));
+    LESASM_HIP_TRY(hipEventCreate(&b->ev1));
+    b->chunk = meshes[0]->chunk_elems;
+    if ((st = build_tables(b)) || (st = build_work(b))) return st;
+    guard.p = nullptr;
+    *out = b;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_batch_destroy(lesasm_batch *b) {
+    batch_free(b);
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_batch_configure(lesasm_batch *b, int chunk, int order, int grid_per_cu) {
+    if (!b) return fail(LESASM_E_INVALID_ARG, "batch_configure: batch is NULL");
+    if (chunk != 0 && (chunk < 32 || chunk > 4096)) return fail(LESASM_E_UNSUPPORTED, "batch_configure: bad chunk");
+    if (order < LESASM_ORDER_MESH || order > LESASM_ORDER_INTERLEAVED)
+        return fail(LESASM_E_UNSUPPORTED, "batch_configure: bad order");
+    if (grid_per_cu < 1 || grid_per_cu > 8) return fail(LESASM_E_UNSUPPORTED, "batch_configure: grid_per_cu in 1..8");
+    b->chunk = chunk;
+    b->order = order;
+    b->grid_per_cu = grid_per_cu;
+    return rebuild(b);
+}
+
+extern "C" int lesasm_batch_get_config(const lesasm_batch *b, int *chunk, int *order, int *grid_per_cu, int *n_items) {
+    if (!b || !chunk || !order || !grid_per_cu || !n_items) return fail(LESASM_E_INVALID_ARG, "batch_get_config: NULL");
+    *chunk = b->chunk;
+    *order = b->order;
+    *grid_per_cu = b->grid_per_cu;
+    *n_items = b->nwork;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_batch_assemble(lesasm_batch *b, const double *const *d_u, const double *const *d_p,
+                                     const double *nu, double *const *d_rhs, void *stream) {
+    if (!b || !d_u || !nu || !d_rhs) return fail(LESASM_E_INVALID_ARG, "batch_assemble: NULL argument");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != b->device) return fail(LESASM_E_STATE, "batch_assemble: wrong current device");
+    BatchCall call;
+    int st = make_call(b, d_u, d_p, nu, d_rhs, call);
+    if (st) return st;
+    const bool fp32 = b->meshes[0]->precision == LESASM_PREC_FP32;
+    return batch_launch(b, call, d_p != nullptr, fp32, (hipStream_t)stream);
+}
+
+// Autotuner: times the batched assembly for every chunk length in `chunks`
+// and every queue order, keeps the fastest.  Results are cached in a text
+// file keyed by the batch signature (meshes' element counts per type, CUs).
+extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, const double *const *d_p,
+                                 const double *nu, double *const *d_rhs, const char *cache_path, int reps,
+                                 double *best_ms) {
+    if (!b || !d_u || !nu || !d_rhs || reps < 1) return fail(LESASM_E_INVALID_ARG, "batch_tune: bad argument");
+    std::ostringstream sig;
+    sig << "cu" << b->n_cu;
+    for (lesasm_mesh *m : b->meshes)
+        for (int k = 0; k < kNumCat; ++k) sig << "_" << m->cat[k].n;
+    const std::string key = sig.str();
+    if (cache_path && *cache_path) {
+        std::ifstream in(cache_path);
+        std::string k;
+        int c, o, g;
+        double ms;
+        while (in >> k >> c >> o >> g >> ms)
+            if (k == key) {
+                b->chunk = c;
+                b->order = o;
+                b->grid_per_cu = g;
+                int st = rebuild(b);
+                if (st) return st;
+                if (best_ms) *best_ms = ms;
+                b->last_tune_ms = ms;
+                return LESASM_OK;
+            }
+    }
+    BatchCall call;
+    int st = make_call(b, d_u, d_p, nu, d_rhs, call);
+    if (st) return st;
+    const bool fp32 = b->meshes[0]->precision == LESASM_PREC_FP32;
+    const int chunks[] = {128, 256, 512, 1024};
+    const int orders[] = {LESASM_ORDER_MESH, LESASM_ORDER_LARGEST_FIRST, LESASM_ORDER_INTERLEAVED};
+    const int grids[] = {2, 4};
+    double best = 1e30;
+    int bc = b->chunk, bo = b->order, bg = b->grid_per_cu;
+    for (int c : chunks) {
+        b->chunk = c;
+        for (int o : orders)
+            for (int g : grids) {
+                b->order = o;
+                b->grid_per_cu = g;
+                if ((st = rebuild(b))) return st;
+                std::vector<float> t;
+                for (int r = 0; r < reps + 1; ++r) {
+                    LESASM_HIP_TRY(hipEventRecord(b->ev0, 0));
+                    if ((st = batch_launch(b, call, d_p != nullptr, fp32, 0))) return st;
+                    LESASM_HIP_TRY(hipEventRecord(b->ev1, 0));
+                    LESASM_HIP_TRY(hipEventSynchronize(b->ev1));
+                    float ms = 0;
+                    LESASM_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+                    if (r) t.push_back(ms);  // first run warms up
+                }
+                std::sort(t.begin(), t.end());
+                const double med = t[t.size() / 2];
+                if (med < best) {
+                    best = med;
+                    bc = c;
+                    bo = o;
+                    bg = g;
+                }
+            }
+    }
+    b->chunk = bc;
+    b->order = bo;
+    b->grid_per_cu = bg;
+    if ((st = rebuild(b))) return st;
+    b->last_tune_ms = best;
+    if (best_ms) *best_ms = best;
+    if (cache_path && *cache_path) {
+        std::ofstream outf(cache_path, std::ios::app);
+        outf << key << " " << bc << " " << bo << " " << bg << " " << best << "\n";
+    }
+    return LESASM_OK;
+}
+
+// Three-stage Runge-Kutta update of every mesh (Heun's third-order tableau;
+// no pressure projection), in place on u, with p fixed:
+//   k1 = dt M^-1 rhs(u);  u2 = u + k1/3;  k2 = dt M^-1 rhs(u2);  u3 = u + 2 k2/3;
+//   k3 = dt M^-1 rhs(u3); u <- u + k1/4 + 3 k3/4.
+static int rk3_record(lesasm_batch *b, double *const *d_u, const double *const *d_p, const double *nu, double dt,
+                      hipStream_t s) {
+    const int n = (int)b->meshes.size();
+    const bool fp32 = b->meshes[0]->precision == LESASM_PREC_FP32;
+    const bool has_p = d_p != nullptr;
+    std::vector<const double *> u_c(n), us_c(n);
+    std::vector<double *> k1(n), k3(n), us(n);
+    for (int i = 0; i < n; ++i) {
+        k1[i] = b->k1 + 3 * b->node_off[i];
+        k3[i] = b->k3 + 3 * b->node_off[i];
+        us[i] = b->us + 3 * b->node_off[i];
+        u_c[i] = d_u[i];
+        us_c[i] = us[i];
+    }
+    const unsigned gridn = (unsigned)((b->total_nodes + 255) / 256);
+    auto stage = [&](const std::vector<const double *> &uin, const std::vector<double *> &rhs, double a1,
+                     const std::vector<double *> *k1v, double a2, std::vector<double *> &y) -> int {
+        BatchCall call;
+        int st = make_call(b, uin.data(), d_p, nu, rhs.data(), call);
+        if (st) return st;
+        if ((st = batch_launch(b, call, has_p, fp32, s))) return st;
+        UpdateArgs ua;
+        std::memset(&ua, 0, sizeof(ua));
+        for (int i = 0; i < n; ++i) {
+            ua.base[i] = d_u[i];
+            ua.rhs[i] = rhs[i];
+            ua.k1[i] = k1v ? (*k1v)[i] : nullptr;
+            ua.y[i] = y[i];
+        }
+        ua.a1 = a1;
+        ua.a2 = a2;
+        ua.dt = dt;
+        hipLaunchKernelGGL(k_batch_update, dim3(gridn), dim3(256), 0, s, ua, b->d_md, b->d_nprefix, n);
+        LESASM_HIP_TRY(hipGetLastError());
+        return LESASM_OK;
+    };
+    std::vector<double *> uout(d_u, d_u + n);
+    int st;
+    if ((st = stage(u_c, k1, 0.0, nullptr, 1.0 / 3.0, us))) return st;   // us = u + k1/3
+    if ((st = stage(us_c, k3, 0.0, nullptr, 2.0 / 3.0, us))) return st;  // us = u + 2 k2/3
+    return stage(us_c, k3, 0.25, &k1, 0.75, uout);                      // u = u + k1/4 + 3 k3/4
+}
+
+extern "C" int lesasm_batch_rk3_graph(lesasm_batch *b, double *const *d_u, const double *const *d_p,
+                                      const double *nu, double dt, void *stream) {
+    if (!b || !d_u || !nu) return fail(LESASM_E_INVALID_ARG, "batch_rk3_graph: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(LESASM_E_INVALID_ARG, "batch_rk3_graph: capture needs a non-default stream");
+    int st;
+    if (!b->k1) {
+        if ((st = balloc(b, &b->k1, 3 * (size_t)b->total_nodes)) || (st = balloc(b, &b->k3, 3 * (size_t)b->total_nodes)) ||
+            (st = balloc(b, &b->us, 3 * (size_t)b->total_nodes)))
+            return st;
+    }
+    if (b->graph_exec) {
+        (void)hipGraphExecDestroy(b->graph_exec);
+        (void)hipGraphDestroy(b->graph);
+        b->graph_exec = nullptr;
+        b->graph = nullptr;
+    }
+    LESASM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = rk3_record(b, d_u, d_p, nu, dt, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LESASM_E_HIP, std::string("batch_rk3_graph: capture failed: ") + hipGetErrorString(e));
+    b->graph = g;
+    LESASM_HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_batch_rk3_launch(lesasm_batch *b, void *stream) {
+    if (!b || !b->graph_exec) return fail(LESASM_E_STATE, "batch_rk3_launch: no captured step");
+    LESASM_HIP_TRY(hipGraphLaunch(b->graph_exec, (hipStream_t)stream));
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_batch_rk3_eager(lesasm_batch *b, double *const *d_u, const double *const *d_p,
+                                      const double *nu, double dt, void *stream) {
+    if (!b || !d_u || !nu) return fail(LESASM_E_INVALID_ARG, "batch_rk3_eager: NULL argument");
+    int st;
+    if (!b->k1) {
+        if ((st = balloc(b, &b->k1, 3 * (size_t)b->total_nodes)) || (st = balloc(b, &b->k3, 3 * (size_t)b->total_nodes)) ||
+            (st = balloc(b, &b->us, 3 * (size_t)b->total_nodes)))
+            return st;
+    }
+    return rk3_record(b, d_u, d_p, nu, dt, (hipStream_t)stream);
+}

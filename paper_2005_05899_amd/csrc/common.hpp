@@ -9,6 +9,8 @@
 
 #include "lesasm.h"
 
+struct lesasm_mesh;
+
 namespace lesasm {
 
 // Brackets one kernel launch with HIP events when the mesh profiles.
@@ -82,6 +84,11 @@ struct ChunkView {
 };
 
 constexpr uint32_t kOwnedBit = 0x80000000u;
+
+// Shared between translation units.
+int grid_for(size_t n, int block);
+int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, double dt, double *rhs, hipStream_t s,
+                  bool increment);
 
 // Arguments of one assembly launch over a contiguous element range of a category.
 struct CatView {

@@ -90,6 +90,27 @@ __device__ __forceinline__ void gather_lds(ElementData<T, R> &d, const int (&lg)
     }
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by two Newton steps (quadratic convergence: ~2^-26 -> ~2^-52 -> below FP64
+// rounding), cheaper than the IEEE division and square-root sequences.
+__device__ __forceinline__ double fast_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+
+__device__ __forceinline__ double fast_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x, y * y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x, y * y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // Vreman: with alpha = G^T, beta = Delta^2 G G^T and alpha:alpha = tr(G G^T).
 // nu_t = c Delta^2 sqrt(B'/A) with B' the sum of the principal 2x2 minors of
 // G G^T (B_beta = Delta^4 B') and A its trace; 0 when A = 0; B' clamped at 0.
@@ -102,9 +123,14 @@ __device__ __forceinline__ R vreman_nut(const R G[3][3], R cd2) {
     const R m02 = G[0][0] * G[2][0] + G[0][1] * G[2][1] + G[0][2] * G[2][2];
     const R m12 = G[1][0] * G[2][0] + G[1][1] * G[2][1] + G[1][2] * G[2][2];
     const R A = m00 + m11 + m22;
-    R B = m00 * m11 - m01 * m01 + m00 * m22 - m02 * m02 + m11 * m22 - m12 * m12;
-    B = B > (R)0 ? B : (R)0;
-    return A > (R)0 ? cd2 * sqrt(B / A) : (R)0;
+    const R B = m00 * m11 - m01 * m01 + m00 * m22 - m02 * m02 + m11 * m22 - m12 * m12;
+    // zero when B <= 0 (clamp) or A = 0.  FP64: sqrt(B/A) = B / sqrt(A B) (no
+    // overflow risk for |G|^6 in FP64); FP32: sqrt(B * (1/A)) keeps the range.
+    if (!(A > (R)0 && B > (R)0)) return (R)0;
+    if constexpr (sizeof(R) == 8)
+        return cd2 * B * fast_rsqrt(A * B);
+    else
+        return cd2 * __builtin_amdgcn_sqrtf(B * fast_rcp(A));
 }
 
 // Residual of one element into acc[a][i] (acc is zeroed here).
@@ -143,7 +169,7 @@ __device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> 
     adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
     adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-    const R rdet = (R)1 / det;
+    const R rdet = fast_rcp(det);
     R G[3][3], q[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -235,7 +261,7 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
         adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
         adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
         const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-        const R rdet = (R)1 / det;
+        const R rdet = fast_rcp(det);
 
         R G[3][3], q[3];
 #pragma unroll
@@ -276,6 +302,79 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
                 }
                 acc[a][i] -= s;
             }
+        }
+    }
+}
+
+// One chunk of consecutive elements, processed by one workgroup.  The
+// chunk's distinct nodes are loaded once into LDS (coordinates, velocity,
+// pressure), every element reads them from there, and element residuals are
+// summed into per-node LDS accumulators.  Afterwards each node is written once:
+// a plain store when every element touching it lies in this chunk (owned), an
+// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
+//   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
+template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
+__device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *lds, const double *__restrict__ xyz,
+                                           const double *__restrict__ u, const double *__restrict__ p, double nu,
+                                           double cv, double *__restrict__ rhs) {
+    constexpr int nn = Ref<T>::nn;
+    const int e0 = c.eoff[j], e1 = c.eoff[j + 1];
+    const int g0 = c.goff[j], ng = c.goff[j + 1] - g0;
+    const int f0 = PERIODIC ? c.foff[j] : g0;
+    const int nf = PERIODIC ? c.foff[j + 1] - f0 : ng;
+    double *sx = lds, *su = sx + 3 * ng, *sp = su + 3 * nf, *sacc = sp + nf;
+
+    for (int k = threadIdx.x; k < ng; k += blockDim.x) {
+        const size_t g = (size_t)c.gnodes[g0 + k];
+        sx[3 * k + 0] = xyz[3 * g + 0];
+        sx[3 * k + 1] = xyz[3 * g + 1];
+        sx[3 * k + 2] = xyz[3 * g + 2];
+    }
+    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+        const size_t f = (size_t)((uint32_t)c.fnodes[f0 + k] & ~kOwnedBit);
+        su[3 * k + 0] = u[3 * f + 0];
+        su[3 * k + 1] = u[3 * f + 1];
+        su[3 * k + 2] = u[3 * f + 2];
+        sp[k] = HAS_P ? p[f] : 0.0;
+        sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
+    }
+    __syncthreads();
+
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int lg[nn], lf[nn];
+#pragma unroll
+        for (int a = 0; a < nn; ++a) {
+            lg[a] = c.lg[(size_t)a * c.ld + e];
+            lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+        }
+        ElementData<T, R> d;
+        gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+        const double dl = c.delta[e];
+        R acc[nn][3];
+        element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)acc[a][i]);
+    }
+    __syncthreads();
+
+    for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+        const uint32_t tag = (uint32_t)c.fnodes[f0 + k];
+        double *dst = rhs + 3 * (size_t)(tag & ~kOwnedBit);
+        if (tag & kOwnedBit) {
+            dst[0] = sacc[3 * k + 0];
+            dst[1] = sacc[3 * k + 1];
+            dst[2] = sacc[3 * k + 2];
+        } else if (STAGED) {
+            double *row = c.stage + 3 * (size_t)c.fslot[f0 + k];
+            row[0] = sacc[3 * k + 0];
+            row[1] = sacc[3 * k + 1];
+            row[2] = sacc[3 * k + 2];
+        } else {
+            unsafeAtomicAdd(dst + 0, sacc[3 * k + 0]);
+            unsafeAtomicAdd(dst + 1, sacc[3 * k + 1]);
+            unsafeAtomicAdd(dst + 2, sacc[3 * k + 2]);
         }
     }
 }

@@ -198,7 +198,7 @@ constexpr int kChunkMaxNodes = 800;
 static int chunk_length(const lesasm_mesh *m, int64_t n) {
     if (m->chunk_elems) return m->chunk_elems;
     int ce = 64;
-    while (ce < 512 && 2 * ce <= n / 1024) ce *= 2;
+    while (ce < 512 && 2 * ce <= n / 256) ce *= 2;
     return ce;
 }
 

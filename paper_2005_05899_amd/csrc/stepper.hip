@@ -1,0 +1,601 @@
+// Fractional-step time integration on the GPU (Section 3.2 and Algorithm 1).
+//
+// Algorithm 1 assembles the Laplacian matrix once before the time loop, then
+// per time step runs three Runge-Kutta stages (element assembly, momentum
+// update) and one pressure solve by Jacobi-preconditioned conjugate gradients.
+// The paper names a third-order Runge-Kutta scheme without its coefficients;
+// the tableau here is Heun's third-order method, c = (0, 1/3, 2/3),
+// a21 = 1/3, a32 = 2/3, b = (1/4, 0, 3/4).  Projection (incremental):
+//   u*     = u^n + dt (k1/4 + 3 k3/4),  k_s = M_L^-1 rhs(u_s, p^n)
+//   K dp   = -(1/dt) D u*   (right-hand side projected to zero mean; dp zero mean)
+//   u^n+1  = u* - dt M_L^-1 G dp,   p^n+1 = p^n + dp
+// with K = int grad N_a . grad N_b, (D u)_a = int N_a div u, (G p)_a = int N_a grad p.
+// Everything is FP64.  These are support operations for the assembly; their
+// element loops use direct FP64 atomics.
+#include <algorithm>
+#include <cmath>
+
+#include "element.hpp"
+
+namespace lesasm {
+
+// ---- element operators -----------------------------------------------------
+
+template <int T>
+__device__ __forceinline__ void load_geometry(const CatView &c, int e, const double *__restrict__ xyz,
+                                              double (&x)[Ref<T>::nn][3], int (&fid)[Ref<T>::nn]) {
+    constexpr int nn = Ref<T>::nn;
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        const int g = c.cg[(size_t)a * c.ld + e];
+        fid[a] = c.cf[(size_t)a * c.ld + e];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[a][k] = xyz[3 * (size_t)g + k];
+    }
+#pragma unroll
+    for (int a = nn - 1; a >= 0; --a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[a][k] -= x[0][k];
+}
+
+// Jacobian at Gauss point g, its inverse (K[k][i] = dxi_k/dx_i) and det.
+template <int T>
+__device__ __forceinline__ double jac_inverse(const double (&x)[Ref<T>::nn][3], int g, double (&Ki)[3][3]) {
+    constexpr int nn = Ref<T>::nn;
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int a = 1; a < nn; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) J[i][k] += x[a][i] * Ref<T>::tab.dN[g][a][k];
+    double adj[3][3];
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+    const double r = 1.0 / det;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Ki[i][k] = adj[i][k] * r;
+    return det;
+}
+
+// (D u)_a += sum_g w det N_a div u
+template <int T>
+__global__ __launch_bounds__(256) void k_divergence(CatView c, const double *__restrict__ xyz,
+                                                    const double *__restrict__ u, double *__restrict__ out) {
+    using E = Ref<T>;
+    constexpr int nn = E::nn;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= c.n) return;
+    double x[nn][3], uu[nn][3], m[nn];
+    int fid[nn];
+    load_geometry<T>(c, e, xyz, x, fid);
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        m[a] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) uu[a][k] = u[3 * (size_t)fid[a] + k];
+    }
+#pragma unroll
+    for (int g = 0; g < E::ng; ++g) {
+        double Ki[3][3];
+        const double det = jac_inverse<T>(x, g, Ki);
+        double div = 0.0;
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double dnx = Ki[0][i] * E::tab.dN[g][a][0] + Ki[1][i] * E::tab.dN[g][a][1] +
+                                   Ki[2][i] * E::tab.dN[g][a][2];
+                div += uu[a][i] * dnx;
+            }
+        const double wd = E::tab.w[g] * det * div;
+#pragma unroll
+        for (int a = 0; a < nn; ++a) m[a] += wd * E::tab.N[g][a];
+    }
+#pragma unroll
+    for (int a = 0; a < nn; ++a) unsafeAtomicAdd(out + fid[a], m[a]);
+}
+
+// (G p)_a += sum_g w det N_a grad p
+template <int T>
+__global__ __launch_bounds__(256) void k_gradient(CatView c, const double *__restrict__ xyz,
+                                                  const double *__restrict__ p, double *__restrict__ out) {
+    using E = Ref<T>;
+    constexpr int nn = E::nn;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= c.n) return;
+    double x[nn][3], pp[nn], m[nn][3];
+    int fid[nn];
+    load_geometry<T>(c, e, xyz, x, fid);
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        pp[a] = p[fid[a]];
+        m[a][0] = m[a][1] = m[a][2] = 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < E::ng; ++g) {
+        double Ki[3][3];
+        const double det = jac_inverse<T>(x, g, Ki);
+        double gp[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                gp[i] += pp[a] * (Ki[0][i] * E::tab.dN[g][a][0] + Ki[1][i] * E::tab.dN[g][a][1] +
+                                  Ki[2][i] * E::tab.dN[g][a][2]);
+        const double wd = E::tab.w[g] * det;
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) m[a][i] += wd * E::tab.N[g][a] * gp[i];
+    }
+#pragma unroll
+    for (int a = 0; a < nn; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) unsafeAtomicAdd(out + 3 * (size_t)fid[a] + i, m[a][i]);
+}
+
+__device__ __forceinline__ int find_col(const int32_t *__restrict__ col, int lo, int hi, int key) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// K_ab += sum_g w det grad N_a . grad N_b into the CSR matrix (rows = field nodes)
+template <int T>
+__global__ __launch_bounds__(256) void k_laplacian(CatView c, const double *__restrict__ xyz,
+                                                   const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, double *__restrict__ val) {
+    using E = Ref<T>;
+    constexpr int nn = E::nn;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= c.n) return;
+    double x[nn][3], Ke[nn][nn];
+    int fid[nn];
+    load_geometry<T>(c, e, xyz, x, fid);
+#pragma unroll
+    for (int a = 0; a < nn; ++a)
+#pragma unroll
+        for (int b = 0; b < nn; ++b) Ke[a][b] = 0.0;
+#pragma unroll
+    for (int g = 0; g < E::ng; ++g) {
+        double Ki[3][3], dx[nn][3];
+        const double det = jac_inverse<T>(x, g, Ki);
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                dx[a][i] = Ki[0][i] * E::tab.dN[g][a][0] + Ki[1][i] * E::tab.dN[g][a][1] +
+                           Ki[2][i] * E::tab.dN[g][a][2];
+        const double wd = E::tab.w[g] * det;
+#pragma unroll
+        for (int a = 0; a < nn; ++a)
+#pragma unroll
+            for (int b = 0; b < nn; ++b) Ke[a][b] += wd * (dx[a][0] * dx[b][0] + dx[a][1] * dx[b][1] + dx[a][2] * dx[b][2]);
+    }
+#pragma unroll
+    for (int a = 0; a < nn; ++a) {
+        const int r0 = rowptr[fid[a]], r1 = rowptr[fid[a] + 1];
+#pragma unroll
+        for (int b = 0; b < nn; ++b) unsafeAtomicAdd(val + find_col(col, r0, r1, fid[b]), Ke[a][b]);
+    }
+}
+
+// ---- vector kernels ----------------------------------------------------------
+
+__global__ void k_spmv(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                       const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ y, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) s += val[q] * x[col[q]];
+    y[i] = s;
+}
+
+constexpr int kRedBlocks = 512;
+
+// Fixed-order two-level reduction: partial[b] = sum over a grid-stride slice.
+__global__ void k_dot_partial(const double *__restrict__ a, const double *__restrict__ b, int n,
+                              double *__restrict__ partial) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        s += b ? a[i] * b[i] : a[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_reduce_final(const double *__restrict__ partial, int nb, double *__restrict__ out) {
+    __shared__ double sh[kRedBlocks];
+    sh[threadIdx.x] = (int)threadIdx.x < nb ? partial[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = kRedBlocks / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// y = a0 x0 + a1 x1 + a2 x2 (x1, x2 may be NULL)
+__global__ void k_lincomb(double *__restrict__ y, double a0, const double *__restrict__ x0, double a1,
+                          const double *__restrict__ x1, double a2, const double *__restrict__ x2, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double v = a0 * x0[i];
+        if (x1) v += a1 * x1[i];
+        if (x2) v += a2 * x2[i];
+        y[i] = v;
+    }
+}
+
+// y[i] += alpha * x[i] with alpha = scale * (*num) / (*den), read on the device
+__global__ void k_axpy_ratio(double *__restrict__ y, const double *__restrict__ x, const double *num,
+                             const double *den, double scale, int n) {
+    const double alpha = scale * (*num) / (*den);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] += alpha * x[i];
+}
+
+// p = z + (num/den) p
+__global__ void k_xpby_ratio(double *__restrict__ p, const double *__restrict__ z, const double *num,
+                             const double *den, int n) {
+    const double beta = (*num) / (*den);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+}
+
+// z = x / d (Jacobi)
+__global__ void k_jacobi(double *__restrict__ z, const double *__restrict__ x, const double *__restrict__ d, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) z[i] = x[i] / d[i];
+}
+
+// x -= (*sum) / n
+__global__ void k_sub_mean(double *__restrict__ x, const double *sum, int n) {
+    const double m = (*sum) / n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] -= m;
+}
+
+__global__ void k_diag(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                       const double *__restrict__ val, double *__restrict__ d, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = 0.0;
+    for (int q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        if (col[q] == i) v = val[q];
+    d[i] = v;
+}
+
+// u_new = u* - dt M^-1 (G dp)
+__global__ void k_correct(double *__restrict__ u, const double *__restrict__ ustar, const double *__restrict__ gdp,
+                          const double *__restrict__ mass, double dt, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double s = dt / mass[i];
+        u[3 * (size_t)i + 0] = ustar[3 * (size_t)i + 0] - s * gdp[3 * (size_t)i + 0];
+        u[3 * (size_t)i + 1] = ustar[3 * (size_t)i + 1] - s * gdp[3 * (size_t)i + 1];
+        u[3 * (size_t)i + 2] = ustar[3 * (size_t)i + 2] - s * gdp[3 * (size_t)i + 2];
+    }
+}
+
+__global__ void k_zero(double *__restrict__ a, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+// Launches KERNEL<type> over every non-empty category of mesh m on stream s.
+#define LESASM_PER_CATEGORY(KERNEL, m, s, ...)                                                              \
+    for (int k_ = 0; k_ < kNumCat; ++k_) {                                                                 \
+        const Category &c_ = (m)->cat[k_];                                                                 \
+        if (c_.n == 0) continue;                                                                           \
+        CatView v_{c_.d_cg, c_.d_cf, c_.d_delta, (int32_t)c_.n, 0, (int32_t)c_.n};                         \
+        const dim3 g_((unsigned)((c_.n + 255) / 256)), b_(256);                                            \
+        switch (c_.type) {                                                                                 \
+        case LESASM_TET04: hipLaunchKernelGGL(KERNEL<LESASM_TET04>, g_, b_, 0, (s), v_, __VA_ARGS__); break; \
+        case LESASM_PYR05: hipLaunchKernelGGL(KERNEL<LESASM_PYR05>, g_, b_, 0, (s), v_, __VA_ARGS__); break; \
+        case LESASM_PEN06: hipLaunchKernelGGL(KERNEL<LESASM_PEN06>, g_, b_, 0, (s), v_, __VA_ARGS__); break; \
+        case LESASM_HEX08: hipLaunchKernelGGL(KERNEL<LESASM_HEX08>, g_, b_, 0, (s), v_, __VA_ARGS__); break; \
+        }                                                                                                  \
+    }
+
+}  // namespace lesasm
+
+using namespace lesasm;
+
+struct lesasm_stepper {
+    lesasm_mesh *mesh = nullptr;
+    double nu = 0.0, dt = 0.0, rtol = 1e-12;
+    int maxit = 1000, check_every = 8;
+    int n = 0;
+    int32_t *rowptr = nullptr, *col = nullptr;
+    double *val = nullptr, *diag = nullptr;
+    double *k1 = nullptr, *k3 = nullptr, *us = nullptr, *ustar = nullptr, *gdp = nullptr;  // [n][3]
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;  // [n]
+    double *partial = nullptr, *scal = nullptr;  // reductions
+    std::vector<void *> allocs;
+    int last_iters = 0;
+    double last_res = 0.0;
+    int64_t nnz = 0;
+};
+
+namespace {
+
+template <class T> int salloc(lesasm_stepper *st, T **p, size_t n) {
+    *p = nullptr;
+    if (!n) return LESASM_OK;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LESASM_E_OOM, "stepper: hipMalloc failed");
+    }
+    st->allocs.push_back(q);
+    *p = (T *)q;
+    return LESASM_OK;
+}
+
+void stepper_free(lesasm_stepper *st) {
+    if (!st) return;
+    (void)hipDeviceSynchronize();
+    for (void *p : st->allocs) (void)hipFree(p);
+    delete st;
+}
+
+enum { S_RZ = 0, S_PQ, S_RR, S_RZN, S_BB, S_SUM, S_NUM };
+
+int dot(lesasm_stepper *st, const double *a, const double *b, int which, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, st->n, st->partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedBlocks), 0, s, st->partial, kRedBlocks, st->scal + which);
+    return LESASM_OK;
+}
+
+int pressure_solve(lesasm_stepper *st, const double *b_in, double *x, hipStream_t s) {
+    const int n = st->n;
+    const int g = grid_for(n, 256);
+    // b = b_in - mean(b_in)
+    LESASM_HIP_TRY(hipMemcpyAsync(st->b, b_in, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    dot(st, st->b, nullptr, S_SUM, s);
+    hipLaunchKernelGGL(k_sub_mean, dim3(g), dim3(256), 0, s, st->b, st->scal + S_SUM, n);
+    dot(st, st->b, st->b, S_BB, s);
+    hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, s, x, (size_t)n);
+    LESASM_HIP_TRY(hipMemcpyAsync(st->r, st->b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(256), 0, s, st->z, st->r, st->diag, n);
+    LESASM_HIP_TRY(hipMemcpyAsync(st->pv, st->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    dot(st, st->r, st->z, S_RZ, s);
+    double host[S_NUM] = {0};
+    LESASM_HIP_TRY(hipMemcpyAsync(host, st->scal, sizeof(host), hipMemcpyDeviceToHost, s));
+    LESASM_HIP_TRY(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(host[S_BB]);
+    int it = 0;
+    double res = bnorm;
+    if (bnorm > 0.0) {
+        for (it = 1; it <= st->maxit; ++it) {
+            hipLaunchKernelGGL(k_spmv, dim3((n + 255) / 256), dim3(256), 0, s, st->rowptr, st->col, st->val, st->pv,
+                               st->q, n);
+            dot(st, st->pv, st->q, S_PQ, s);
+            hipLaunchKernelGGL(k_axpy_ratio, dim3(g), dim3(256), 0, s, x, st->pv, st->scal + S_RZ, st->scal + S_PQ,
+                               1.0, n);
+            hipLaunchKernelGGL(k_axpy_ratio, dim3(g), dim3(256), 0, s, st->r, st->q, st->scal + S_RZ,
+                               st->scal + S_PQ, -1.0, n);
+            hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(256), 0, s, st->z, st->r, st->diag, n);
+            dot(st, st->r, st->z, S_RZN, s);
+            hipLaunchKernelGGL(k_xpby_ratio, dim3(g), dim3(256), 0, s, st->pv, st->z, st->scal + S_RZN,
+                               st->scal + S_RZ, n);
+            LESASM_HIP_TRY(hipMemcpyAsync(st->scal + S_RZ, st->scal + S_RZN, sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (it % st->check_every == 0 || it == st->maxit) {
+                dot(st, st->r, st->r, S_RR, s);
+                LESASM_HIP_TRY(hipMemcpyAsync(host, st->scal, sizeof(host), hipMemcpyDeviceToHost, s));
+                LESASM_HIP_TRY(hipStreamSynchronize(s));
+                res = std::sqrt(host[S_RR]);
+                if (res <= st->rtol * bnorm) break;
+            }
+        }
+    }
+    st->last_iters = std::min(it, st->maxit);
+    st->last_res = bnorm > 0.0 ? res / bnorm : 0.0;
+    dot(st, x, nullptr, S_SUM, s);
+    hipLaunchKernelGGL(k_sub_mean, dim3(g), dim3(256), 0, s, x, st->scal + S_SUM, n);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+}  // namespace
+
+extern "C" int lesasm_divergence(lesasm_mesh *m, const double *d_u, double *d_out, void *stream) {
+    if (!m || (m->n_field && (!d_u || !d_out))) return fail(LESASM_E_INVALID_ARG, "divergence: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!m->n_field) return LESASM_OK;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(m->n_field, 256)), dim3(256), 0, s, d_out, (size_t)m->n_field);
+    LESASM_PER_CATEGORY(k_divergence, m, s, (const double *)m->d_xyz, d_u, d_out);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_gradient(lesasm_mesh *m, const double *d_p, double *d_out, void *stream) {
+    if (!m || (m->n_field && (!d_p || !d_out))) return fail(LESASM_E_INVALID_ARG, "gradient: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!m->n_field) return LESASM_OK;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(3 * (size_t)m->n_field, 256)), dim3(256), 0, s, d_out,
+                       3 * (size_t)m->n_field);
+    LESASM_PER_CATEGORY(k_gradient, m, s, (const double *)m->d_xyz, d_p, d_out);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_create(lesasm_mesh *m, double nu, double dt, double rtol, int maxit,
+                                     lesasm_stepper **out) {
+    if (!out) return fail(LESASM_E_INVALID_ARG, "stepper_create: out is NULL");
+    *out = nullptr;
+    if (!m || !(dt > 0.0) || !(rtol > 0.0) || maxit < 1)
+        return fail(LESASM_E_INVALID_ARG, "stepper_create: need a mesh, dt > 0, rtol > 0, maxit >= 1");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device) return fail(LESASM_E_STATE, "stepper_create: current device differs from the mesh's");
+    auto *st = new lesasm_stepper();
+    struct Guard {
+        lesasm_stepper *p;
+        ~Guard() { stepper_free(p); }
+    } guard{st};
+    st->mesh = m;
+    st->nu = nu;
+    st->dt = dt;
+    st->rtol = rtol;
+    st->maxit = maxit;
+    st->n = (int)m->n_field;
+    const int n = st->n;
+
+    // CSR pattern of K: for each field node, the field nodes of its elements
+    std::vector<int32_t> ninc(n + 1, 0);
+    for (int k = 0; k < kNumCat; ++k) {
+        const Category &c = m->cat[k];
+        const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
+        for (int32_t f : cf) ninc[f + 1]++;
+    }
+    for (int i = 0; i < n; ++i) ninc[i + 1] += ninc[i];
+    std::vector<int64_t> elem_of(ninc[n]);
+    std::vector<int32_t> fill(ninc.begin(), ninc.end() - 1);
+    int64_t gbase = 0;
+    for (int k = 0; k < kNumCat; ++k) {
+        const Category &c = m->cat[k];
+        const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
+        for (int a = 0; a < c.type; ++a)
+            for (int64_t e = 0; e < c.n; ++e) elem_of[fill[cf[(size_t)a * c.n + e]]++] = gbase + e;
+        gbase += c.n;
+    }
+    auto elem_nodes = [&](int64_t ge, std::vector<int32_t> &outv) {
+        for (int k = 0; k < kNumCat; ++k) {
+            const Category &c = m->cat[k];
+            if (ge < c.first || ge >= c.first + c.n) continue;
+            const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
+            for (int a = 0; a < c.type; ++a) outv.push_back(cf[(size_t)a * c.n + (ge - c.first)]);
+            return;
+        }
+    };
+    std::vector<int32_t> rowptr(n + 1, 0), col, tmp;
+    for (int i = 0; i < n; ++i) {
+        tmp.clear();
+        tmp.push_back(i);
+        for (int32_t q = ninc[i]; q < ninc[i + 1]; ++q) elem_nodes(elem_of[q], tmp);
+        std::sort(tmp.begin(), tmp.end());
+        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+        col.insert(col.end(), tmp.begin(), tmp.end());
+        rowptr[i + 1] = (int32_t)col.size();
+    }
+    st->nnz = (int64_t)col.size();
+    int rc;
+    if ((rc = salloc(st, &st->rowptr, rowptr.size())) || (rc = salloc(st, &st->col, col.size())) ||
+        (rc = salloc(st, &st->val, col.size())) || (rc = salloc(st, &st->diag, (size_t)n)) ||
+        (rc = salloc(st, &st->k1, 3 * (size_t)n)) || (rc = salloc(st, &st->k3, 3 * (size_t)n)) ||
+        (rc = salloc(st, &st->us, 3 * (size_t)n)) || (rc = salloc(st, &st->ustar, 3 * (size_t)n)) ||
+        (rc = salloc(st, &st->gdp, 3 * (size_t)n)) || (rc = salloc(st, &st->b, (size_t)n)) ||
+        (rc = salloc(st, &st->x, (size_t)n)) || (rc = salloc(st, &st->r, (size_t)n)) ||
+        (rc = salloc(st, &st->z, (size_t)n)) || (rc = salloc(st, &st->pv, (size_t)n)) ||
+        (rc = salloc(st, &st->q, (size_t)n)) || (rc = salloc(st, &st->partial, kRedBlocks)) ||
+        (rc = salloc(st, &st->scal, S_NUM)))
+        return rc;
+    if (n) {
+        LESASM_HIP_TRY(hipMemcpy(st->rowptr, rowptr.data(), sizeof(int32_t) * rowptr.size(), hipMemcpyHostToDevice));
+        LESASM_HIP_TRY(hipMemcpy(st->col, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice));
+        LESASM_HIP_TRY(hipMemset(st->val, 0, sizeof(double) * col.size()));
+        hipStream_t s0 = 0;
+        LESASM_PER_CATEGORY(k_laplacian, m, s0, (const double *)m->d_xyz, (const int32_t *)st->rowptr,
+                            (const int32_t *)st->col, st->val);
+        hipLaunchKernelGGL(k_diag, dim3((n + 255) / 256), dim3(256), 0, 0, st->rowptr, st->col, st->val, st->diag, n);
+        LESASM_HIP_TRY(hipGetLastError());
+        LESASM_HIP_TRY(hipDeviceSynchronize());
+    }
+    guard.p = nullptr;
+    *out = st;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_destroy(lesasm_stepper *st) {
+    stepper_free(st);
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_laplacian(lesasm_stepper *st, int32_t *rowptr, int32_t *col, double *val, int64_t *nnz) {
+    if (!st || !nnz) return fail(LESASM_E_INVALID_ARG, "stepper_laplacian: NULL argument");
+    *nnz = st->nnz;
+    if (rowptr) LESASM_HIP_TRY(hipMemcpy(rowptr, st->rowptr, sizeof(int32_t) * (st->n + 1), hipMemcpyDeviceToHost));
+    if (col) LESASM_HIP_TRY(hipMemcpy(col, st->col, sizeof(int32_t) * st->nnz, hipMemcpyDeviceToHost));
+    if (val) LESASM_HIP_TRY(hipMemcpy(val, st->val, sizeof(double) * st->nnz, hipMemcpyDeviceToHost));
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_pressure_solve(lesasm_stepper *st, const double *d_b, double *d_x, void *stream) {
+    if (!st || (st->n && (!d_b || !d_x))) return fail(LESASM_E_INVALID_ARG, "pressure_solve: NULL argument");
+    if (!st->n) return LESASM_OK;
+    return pressure_solve(st, d_b, d_x, (hipStream_t)stream);
+}
+
+// Three explicit stages only: d_ustar = u^n + dt (k1/4 + 3 k3/4).
+static int rk3_stages(lesasm_stepper *st, const double *u, const double *p, double *ustar, hipStream_t s) {
+    lesasm_mesh *m = st->mesh;
+    const size_t n3 = 3 * (size_t)st->n;
+    const int g = grid_for(n3, 256);
+    int rc;
+    // stage 1: k1 = dt M^-1 rhs(u^n); u2 = u^n + k1/3
+    if ((rc = assemble_into(m, u, p, st->nu, st->dt, st->k1, s, true))) return rc;
+    hipLaunchKernelGGL(k_lincomb, dim3(g), dim3(256), 0, s, st->us, 1.0, u, 1.0 / 3.0, st->k1, 0.0, nullptr, n3);
+    // stage 2: k2 = dt M^-1 rhs(u2); u3 = u^n + 2 k2/3   (k2 held in k3)
+    if ((rc = assemble_into(m, st->us, p, st->nu, st->dt, st->k3, s, true))) return rc;
+    hipLaunchKernelGGL(k_lincomb, dim3(g), dim3(256), 0, s, st->us, 1.0, u, 2.0 / 3.0, st->k3, 0.0, nullptr, n3);
+    // stage 3: k3 = dt M^-1 rhs(u3); u* = u^n + k1/4 + 3 k3/4
+    if ((rc = assemble_into(m, st->us, p, st->nu, st->dt, st->k3, s, true))) return rc;
+    hipLaunchKernelGGL(k_lincomb, dim3(g), dim3(256), 0, s, ustar, 1.0, u, 0.25, st->k1, 0.75, st->k3, n3);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_rk3_stages(lesasm_stepper *st, const double *d_u, const double *d_p, double *d_ustar,
+                                         void *stream) {
+    if (!st || (st->n && (!d_u || !d_ustar))) return fail(LESASM_E_INVALID_ARG, "rk3_stages: NULL argument");
+    if (!st->n) return LESASM_OK;
+    return rk3_stages(st, d_u, d_p, d_ustar, (hipStream_t)stream);
+}
+
+extern "C" int lesasm_stepper_step(lesasm_stepper *st, double *d_u, double *d_p, void *stream) {
+    if (!st || (st->n && (!d_u || !d_p))) return fail(LESASM_E_INVALID_ARG, "stepper_step: NULL argument");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != st->mesh->device) return fail(LESASM_E_STATE, "stepper_step: wrong current device");
+    if (!st->n) return LESASM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    lesasm_mesh *m = st->mesh;
+    const int n = st->n;
+    int rc;
+    if ((rc = rk3_stages(st, d_u, d_p, st->ustar, s))) return rc;
+    // b = -(1/dt) D u*
+    if ((rc = lesasm_divergence(m, st->ustar, st->q, s))) return rc;
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, 256)), dim3(256), 0, s, st->q, -1.0 / st->dt, st->q, 0.0, nullptr,
+                       0.0, nullptr, (size_t)n);
+    if ((rc = pressure_solve(st, st->q, st->x, s))) return rc;
+    if ((rc = lesasm_gradient(m, st->x, st->gdp, s))) return rc;
+    hipLaunchKernelGGL(k_correct, dim3(grid_for(n, 256)), dim3(256), 0, s, d_u, st->ustar, st->gdp, m->d_mass,
+                       st->dt, n);
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, 256)), dim3(256), 0, s, d_p, 1.0, d_p, 1.0, st->x, 0.0, nullptr,
+                       (size_t)n);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_stats(const lesasm_stepper *st, int *cg_iters, double *cg_rel_residual) {
+    if (!st || !cg_iters || !cg_rel_residual) return fail(LESASM_E_INVALID_ARG, "stepper_stats: NULL argument");
+    *cg_iters = st->last_iters;
+    *cg_rel_residual = st->last_res;
+    return LESASM_OK;
+}

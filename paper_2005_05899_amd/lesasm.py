@@ -29,7 +29,13 @@ EXPORTS = [
     "lesasm_mesh_element_permutation", "lesasm_fields_to_internal", "lesasm_fields_to_user",
     "lesasm_mesh_lumped_mass", "lesasm_mesh_filter_width", "lesasm_mesh_set_option", "lesasm_mesh_get_option",
     "lesasm_assemble_momentum_rhs", "lesasm_mesh_kernel_times", "lesasm_last_error", "lesasm_version",
+    "lesasm_divergence", "lesasm_gradient", "lesasm_stepper_create", "lesasm_stepper_destroy", "lesasm_stepper_step",
+    "lesasm_stepper_rk3_stages", "lesasm_pressure_solve", "lesasm_stepper_stats", "lesasm_stepper_laplacian",
+    "lesasm_batch_create", "lesasm_batch_destroy", "lesasm_batch_configure", "lesasm_batch_get_config",
+    "lesasm_batch_assemble", "lesasm_batch_tune", "lesasm_batch_rk3_graph", "lesasm_batch_rk3_launch",
+    "lesasm_batch_rk3_eager",
 ]
+ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
 
 
 class LesasmError(RuntimeError):
@@ -74,7 +80,14 @@ def load(path: str = LIB_PATH):
         "lesasm_mesh_lumped_mass": [P, P, P], "lesasm_mesh_filter_width": [P, P, P],
         "lesasm_mesh_set_option": [P, I, I64], "lesasm_mesh_get_option": [P, I, P],
         "lesasm_assemble_momentum_rhs": [P, P, P, D, D, P, P], "lesasm_mesh_kernel_times": [P, P, P, I],
-        "lesasm_version": [],
+        "lesasm_version": [], "lesasm_divergence": [P, P, P, P], "lesasm_gradient": [P, P, P, P],
+        "lesasm_stepper_create": [P, D, D, D, I, P], "lesasm_stepper_destroy": [P], "lesasm_stepper_step": [P, P, P, P],
+        "lesasm_stepper_rk3_stages": [P, P, P, P, P], "lesasm_pressure_solve": [P, P, P, P],
+        "lesasm_stepper_stats": [P, P, P], "lesasm_stepper_laplacian": [P, P, P, P, P],
+        "lesasm_batch_create": [P, I, P], "lesasm_batch_destroy": [P], "lesasm_batch_configure": [P, I, I, I],
+        "lesasm_batch_get_config": [P, P, P, P, P], "lesasm_batch_assemble": [P, P, P, P, P, P],
+        "lesasm_batch_tune": [P, P, P, P, P, ctypes.c_char_p, I, P], "lesasm_batch_rk3_graph": [P, P, P, P, D, P],
+        "lesasm_batch_rk3_launch": [P, P], "lesasm_batch_rk3_eager": [P, P, P, P, D, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -227,3 +240,135 @@ class Mesh:
         check(load().lesasm_assemble_momentum_rhs(self._h, _ptr(u), _ptr(p), float(nu), float(dt), _ptr(out),
                                                   _stream()))
         return out
+
+
+class Stepper:
+    """Fractional-step time integration on a mesh (lesasm_stepper_*)."""
+
+    def __init__(self, mesh: Mesh, nu: float, dt: float, rtol: float = 1e-12, maxit: int = 2000):
+        self.mesh = mesh
+        h = ctypes.c_void_p()
+        check(load().lesasm_stepper_create(mesh._h, float(nu), float(dt), float(rtol), int(maxit), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lesasm_stepper_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, u, p):
+        """One time step in place on internal-order tensors u [n,3], p [n]."""
+        self.mesh._field(u)
+        self.mesh._field(p)
+        check(load().lesasm_stepper_step(self._h, _ptr(u), _ptr(p), _stream()))
+
+    def rk3_stages(self, u, p):
+        out = torch.empty_like(u)
+        check(load().lesasm_stepper_rk3_stages(self._h, _ptr(u), _ptr(p), _ptr(out), _stream()))
+        return out
+
+    def pressure_solve(self, b):
+        x = torch.empty_like(b)
+        check(load().lesasm_pressure_solve(self._h, _ptr(b), _ptr(x), _stream()))
+        return x
+
+    def stats(self):
+        it, res = ctypes.c_int(), ctypes.c_double()
+        check(load().lesasm_stepper_stats(self._h, ctypes.byref(it), ctypes.byref(res)))
+        return it.value, res.value
+
+    def laplacian(self):
+        """(rowptr, col, val) host arrays of the assembled K (internal order)."""
+        nnz = ctypes.c_int64()
+        check(load().lesasm_stepper_laplacian(self._h, None, None, None, ctypes.byref(nnz)))
+        rowptr = np.empty(self.mesh.n_field_nodes + 1, np.int32)
+        col = np.empty(nnz.value, np.int32)
+        val = np.empty(nnz.value, np.float64)
+        check(load().lesasm_stepper_laplacian(self._h, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                              ctypes.byref(nnz)))
+        return rowptr, col, val
+
+
+def divergence(mesh: Mesh, u):
+    out = torch.empty(mesh.n_field_nodes, dtype=torch.float64, device=u.device)
+    check(load().lesasm_divergence(mesh._h, _ptr(u), _ptr(out), _stream()))
+    return out
+
+
+def gradient(mesh: Mesh, p):
+    out = torch.empty((mesh.n_field_nodes, 3), dtype=torch.float64, device=p.device)
+    check(load().lesasm_gradient(mesh._h, _ptr(p), _ptr(out), _stream()))
+    return out
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+class Batch:
+    """Many meshes assembled by one persistent launch (lesasm_batch_*)."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        check(load().lesasm_batch_create(arr, len(self.meshes), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lesasm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def configure(self, chunk: int = 0, order: int = ORDER_MESH, grid_per_cu: int = 2):
+        check(load().lesasm_batch_configure(self._h, int(chunk), int(order), int(grid_per_cu)))
+
+    def config(self) -> dict:
+        c, o, g, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(load().lesasm_batch_get_config(self._h, ctypes.byref(c), ctypes.byref(o), ctypes.byref(g), ctypes.byref(n)))
+        return {"chunk": c.value, "order": o.value, "grid_per_cu": g.value, "items": n.value}
+
+    def _args(self, us, ps, nus):
+        nu = (ctypes.c_double * len(nus))(*[float(v) for v in nus])
+        return _ptrs(us), (None if ps is None else _ptrs(ps)), nu
+
+    def assemble(self, us, ps, nus, outs=None):
+        if outs is None:
+            outs = [torch.empty_like(u) for u in us]
+        u, p, nu = self._args(us, ps, nus)
+        check(load().lesasm_batch_assemble(self._h, u, p, nu, _ptrs(outs), _stream()))
+        return outs
+
+    def tune(self, us, ps, nus, outs, cache_path: str | None = None, reps: int = 3) -> float:
+        u, p, nu = self._args(us, ps, nus)
+        best = ctypes.c_double()
+        check(load().lesasm_batch_tune(self._h, u, p, nu, _ptrs(outs),
+                                       None if cache_path is None else cache_path.encode(), int(reps),
+                                       ctypes.byref(best)))
+        return best.value
+
+    def rk3_graph(self, us, ps, nus, dt: float, stream):
+        """Capture the three-stage update of all meshes on `stream` (a torch.cuda.Stream)."""
+        u, p, nu = self._args(us, ps, nus)
+        self._keep = (u, p, nu)
+        check(load().lesasm_batch_rk3_graph(self._h, u, p, nu, float(dt), ctypes.c_void_p(stream.cuda_stream)))
+
+    def rk3_launch(self, stream=None):
+        s = torch.cuda.current_stream() if stream is None else stream
+        check(load().lesasm_batch_rk3_launch(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def rk3_eager(self, us, ps, nus, dt: float):
+        u, p, nu = self._args(us, ps, nus)
+        check(load().lesasm_batch_rk3_eager(self._h, u, p, nu, float(dt), _stream()))

@@ -1,0 +1,129 @@
+"""Batched persistent assembly, autotuner and graph-captured RK3 stages
+against per-mesh assembly and the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2005_05899_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def batch_setup(torch_cuda):
+    """Five uneven partitions (different sizes, layer mixes and seeds)."""
+    import oracle
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    specs = [(9, 7, [(mg.PEN06, 2), (mg.TET04, 3), (mg.PYR05, 1), (mg.HEX08, 2)]),
+             (4, 3, [(mg.TET04, 2)]),
+             (12, 10, [(mg.PEN06, 3), (mg.TET04, 2), (mg.PYR05, 2), (mg.HEX08, 4)]),
+             (5, 5, [(mg.HEX08, 3)]),
+             (7, 4, [(mg.PYR05, 2), (mg.HEX08, 1)])]
+    cases, meshes, us, ps, refs = [], [], [], [], []
+    for i, (nx, ny, layers) in enumerate(specs):
+        c = mg.small_hybrid_case(nx=nx, ny=ny, layers=layers, seed=40 + i)
+        c.nu = 0.01 * (i + 1)
+        m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+        cases.append(c)
+        meshes.append(m)
+        us.append(m.to_internal(torch.from_numpy(c.u).cuda()))
+        ps.append(m.to_internal(torch.from_numpy(c.p).cuda()))
+        refs.append(oracle.assemble(c.mesh, c.u, c.p, c.nu, c.vreman_c))
+    b = lesasm.Batch(meshes)
+    yield cases, meshes, us, ps, refs, b
+    b.close()
+    for m in meshes:
+        m.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 64, 512])
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_batch_matches_oracle(torch_cuda, batch_setup, chunk, order):
+    torch = torch_cuda
+    cases, meshes, us, ps, refs, b = batch_setup
+    b.configure(chunk=chunk, order=order, grid_per_cu=2)
+    outs = [torch.full_like(u, float("nan")) for u in us]
+    b.assemble(us, ps, [c.nu for c in cases], outs)
+    torch.cuda.synchronize()
+    for c, m, o, ref in zip(cases, meshes, outs, refs):
+        got = m.to_user(o).cpu().numpy()
+        assert rel(got, ref) < TOL64, (c.name, chunk, order)
+
+
+def test_batch_equals_per_mesh_assembly(torch_cuda, batch_setup):
+    torch = torch_cuda
+    cases, meshes, us, ps, refs, b = batch_setup
+    b.configure(chunk=256, order=1, grid_per_cu=4)
+    outs = b.assemble(us, ps, [c.nu for c in cases])
+    single = [m.assemble_momentum_rhs(u, p, c.nu) for m, u, p, c in zip(meshes, us, ps, cases)]
+    torch.cuda.synchronize()
+    for o, s in zip(outs, single):
+        assert rel(o.cpu().numpy(), s.cpu().numpy()) < 1e-13
+
+
+def test_autotuner_and_cache(torch_cuda, batch_setup, tmp_path):
+    torch = torch_cuda
+    cases, meshes, us, ps, refs, b = batch_setup
+    outs = [torch.empty_like(u) for u in us]
+    cache = str(tmp_path / "tune.txt")
+    best = b.tune(us, ps, [c.nu for c in cases], outs, cache, reps=2)
+    cfg = b.config()
+    assert best > 0 and cfg["chunk"] in (128, 256, 512, 1024)
+    lines = open(cache).read().split("\n")
+    assert len([ln for ln in lines if ln.strip()]) == 1
+    b.configure(chunk=64, order=0, grid_per_cu=2)
+    again = b.tune(us, ps, [c.nu for c in cases], outs, cache, reps=2)
+    assert b.config() == cfg and again == pytest.approx(best)
+    b.assemble(us, ps, [c.nu for c in cases], outs)
+    torch.cuda.synchronize()
+    for m, o, ref in zip(meshes, outs, refs):
+        assert rel(m.to_user(o).cpu().numpy(), ref) < TOL64
+
+
+def test_rk3_stages_match_oracle(torch_cuda, batch_setup):
+    from oracle import step
+    torch = torch_cuda
+    cases, meshes, us, ps, refs, b = batch_setup
+    b.configure(chunk=0, order=0, grid_per_cu=2)
+    dt = 0.01
+    u_work = [u.clone() for u in us]
+    b.rk3_eager(u_work, ps, [c.nu for c in cases], dt)
+    torch.cuda.synchronize()
+    for c, m, uw in zip(cases, meshes, u_work):
+        ref = step.rk3_momentum(c.mesh, c.u, c.p, c.nu, c.vreman_c, dt)
+        assert rel(m.to_user(uw).cpu().numpy(), ref) < TOL64
+
+
+def test_graph_replays_match_eager(torch_cuda, batch_setup):
+    """Replay the captured step several times with eager work and
+    synchronisation in between; every replay equals the eager sequence."""
+    torch = torch_cuda
+    cases, meshes, us, ps, refs, b = batch_setup
+    b.configure(chunk=0, order=1, grid_per_cu=2)
+    nus = [c.nu for c in cases]
+    dt = 0.005
+    ug = [u.clone() for u in us]
+    ue = [u.clone() for u in us]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    b.rk3_graph(ug, ps, nus, dt, s)
+    for rep in range(3):
+        b.rk3_launch(s)
+        s.synchronize()
+        b.rk3_eager(ue, ps, nus, dt)
+        torch.cuda.synchronize()
+        for g, e in zip(ug, ue):
+            assert rel(g.cpu().numpy(), e.cpu().numpy()) < 1e-13, rep
