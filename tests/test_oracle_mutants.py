@@ -12,7 +12,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lesasm_oracle.c")
 PINS = ["tests/test_oracle_refelem.py", "tests/test_oracle_vreman.py", "tests/test_oracle_exact.py",
-        "tests/test_oracle_invariants.py", "tests/test_oracle_step.py"]
+        "tests/test_oracle_invariants.py", "tests/test_oracle_step.py", "tests/test_oracle_closure.py"]
 
 MUTANTS = {
     "gradient_uses_J_inverse_untransposed": ("s += K[j][i] * dN[3 * a + j];", "s += K[i][j] * dN[3 * a + j];"),
@@ -62,6 +62,6 @@ def test_unmodified_copy_passes(tmp_path):
 def test_pins_catch_mutant(name, tmp_path):
     old, new = MUTANTS[name]
     src = open(SRC).read()
-    assert src.count(old) == 1, name
+    assert src.count(old) >= 1, name  # every copy of the line gets the same bug
     r = _run_pins(src.replace(old, new), tmp_path)
     assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
