@@ -74,6 +74,7 @@ extern "C" {
                                                device atomics instead of staging rows */
 
 typedef struct lesasm_mesh lesasm_mesh;
+typedef struct lesasm_mlp lesasm_mlp;
 
 /* Host description of a mesh.  All arrays are host memory, read during
  * lesasm_mesh_create only (the library keeps its own device copies).
@@ -295,6 +296,55 @@ int lesasm_batch_rk3_graph(lesasm_batch *batch, double *const *d_u, const double
 int lesasm_batch_rk3_launch(lesasm_batch *batch, void *stream);
 int lesasm_batch_rk3_eager(lesasm_batch *batch, double *const *d_u, const double *const *d_p, const double *nu,
                            double dt, void *stream);
+
+/* ---- learned subgrid closure -------------------------------------------- */
+/* A 10-64-64-6 perceptron replaces Vreman's subgrid stress at the Gauss
+ * points (the subgrid term div(tau) of Section 3.2's momentum equation; the
+ * paper itself uses Vreman).  Inputs x = [G/|G|_F (9, row-major du_i/dx_j),
+ * log(Delta_e/Delta_ref)]; h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2),
+ * y = h2 W3 + b3 with components (xx, yy, zz, xy, xz, yz); the stress is
+ * tau = Delta_e^2 |G|_F^2 dev(y).  Parameters: 5254 floats in the order
+ * W1[10][64], b1[64], W2[64][64], b2[64], W3[64][6], b3[6].               */
+#define LESASM_MLP_PARAMS 5254
+
+/* Device copy of the parameters (FP32 master), Adam moments, and the packed
+ * BF16 matrix-core operands used by inference.  `params` is host memory. */
+int lesasm_mlp_create(const float *params, lesasm_mlp **out);
+int lesasm_mlp_destroy(lesasm_mlp *mlp);
+int lesasm_mlp_get_params(const lesasm_mlp *mlp, float *params);
+/* Replace the parameters (host array), reset Adam, repack (synchronises). */
+int lesasm_mlp_set_params(lesasm_mlp *mlp, const float *params);
+
+/* Training, FP32 on the device.  d_x [n][10] inputs, d_t [n][6] targets for
+ * dev(y).  Loss L = (1/n) sum w_c (dev(y) - t)_c^2, w = (1,1,1,2,2,2).
+ * loss_grad writes dL/dparams to d_grad[5254] (or an internal buffer if NULL)
+ * and L to *d_loss (device float, may be NULL); adam applies one step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) with the given or internal gradient;
+ * train_step = loss_grad + adam.  Asynchronous.  After training, call
+ * lesasm_mlp_commit to refresh the BF16 inference copy (synchronises). */
+int lesasm_mlp_loss_grad(lesasm_mlp *mlp, const float *d_x, const float *d_t, int n, float *d_grad, float *d_loss,
+                         void *stream);
+int lesasm_mlp_adam(lesasm_mlp *mlp, const float *d_grad, float lr, void *stream);
+int lesasm_mlp_train_step(lesasm_mlp *mlp, const float *d_x, const float *d_t, int n, float lr, float *d_loss,
+                          void *stream);
+int lesasm_mlp_commit(lesasm_mlp *mlp);
+
+/* Inference of y (before the trace removal) for n samples, d_y [n][6]:
+ * _f32 with the FP32 master weights, _bf16 with the matrix-core path the
+ * assembly uses (BF16 operands, FP32 sums).  Asynchronous. */
+int lesasm_mlp_forward_f32(lesasm_mlp *mlp, const float *d_x, int n, float *d_y, void *stream);
+int lesasm_mlp_infer_bf16(lesasm_mlp *mlp, const float *d_x, int n, float *d_y, void *stream);
+
+/* Use the network as the subgrid closure of a mesh (mlp = NULL restores
+ * Vreman).  Per element both closures are integrated; the network's residual
+ * is kept unless |R_mlp - R_vreman|_2 > fallback_tol |R_vreman|_2 (element
+ * vectors), in which case Vreman's is used.  Chunked scatters only; the mlp
+ * must outlive its use.  Rebuilds the chunks (synchronises). */
+int lesasm_mesh_set_closure(lesasm_mesh *mesh, const lesasm_mlp *mlp, double delta_ref, double fallback_tol);
+
+/* Number of elements that fell back to Vreman since the last call (resets;
+ * synchronises). */
+int lesasm_mesh_closure_fallbacks(lesasm_mesh *mesh, uint64_t *count);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *lesasm_last_error(void);

@@ -8,6 +8,7 @@
 // threads of a launch touch the same node and the scatter is a plain
 // read-modify-write with a fixed summation order.
 #include <algorithm>
+#include <cmath>
 
 #include "element.hpp"
 
@@ -47,6 +48,18 @@ __global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const doubl
                                                         double *__restrict__ rhs) {
     extern __shared__ double lds[];
     chunk_body<T, R, HAS_P, PERIODIC, STAGED>(c, xcd_block(blockIdx.x, gridDim.x), lds, xyz, u, p, nu, cv, rhs);
+}
+
+// The same with the learned closure (network weights after the node data in LDS).
+template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
+__global__ __launch_bounds__(256) void k_assemble_chunk_mlp(ChunkView c, const double *__restrict__ xyz,
+                                                            const double *__restrict__ u,
+                                                            const double *__restrict__ p, double nu, double cv,
+                                                            double *__restrict__ rhs, ClosureView cl,
+                                                            int lds_node_doubles) {
+    extern __shared__ double lds[];
+    chunk_body<T, R, HAS_P, PERIODIC, STAGED, true>(c, xcd_block(blockIdx.x, gridDim.x), lds, xyz, u, p, nu, cv,
+                                                    rhs, &cl, lds_node_doubles);
 }
 
 // Staged scatter, second phase: every node owned by no chunk sums its staging
@@ -116,31 +129,46 @@ static void dispatch_scatter(const CatView &v, bool atomic, bool has_p, int bloc
     }
 }
 
-template <int T, typename R, bool STAGED>
-static void launch_chunks(const ChunkView &v, int n_chunks, size_t shm, bool has_p, bool periodic, int block,
-                          hipStream_t s, const double *xyz, const double *u, const double *p, double nu, double cv,
-                          double *rhs) {
+template <int T, typename R, bool STAGED, bool HAS_P, bool PERIODIC>
+static void launch_chunk_kernel(const ChunkView &v, int n_chunks, size_t shm, const ClosureView *cl, int block,
+                                hipStream_t s, const double *xyz, const double *u, const double *p, double nu,
+                                double cv, double *rhs) {
     const dim3 grid(n_chunks), blk(block);
-    if (periodic) {
-        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, true, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
-        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, true, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+    if (cl) {
+        const size_t shm_mlp = shm + kMlpLdsBytes + (size_t)(block / 64) * kMlpWaveScratch;
+        hipLaunchKernelGGL((k_assemble_chunk_mlp<T, R, HAS_P, PERIODIC, STAGED>), grid, blk, shm_mlp, s, v, xyz, u, p,
+                           nu, cv, rhs, *cl, (int)(shm / sizeof(double)));
     } else {
-        if (has_p) hipLaunchKernelGGL((k_assemble_chunk<T, R, true, false, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
-        else hipLaunchKernelGGL((k_assemble_chunk<T, R, false, false, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv, rhs);
+        hipLaunchKernelGGL((k_assemble_chunk<T, R, HAS_P, PERIODIC, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv,
+                           rhs);
+    }
+}
+
+template <int T, typename R, bool STAGED>
+static void launch_chunks(const ChunkView &v, int n_chunks, size_t shm, const ClosureView *cl, bool has_p,
+                          bool periodic, int block, hipStream_t s, const double *xyz, const double *u,
+                          const double *p, double nu, double cv, double *rhs) {
+    if (periodic) {
+        if (has_p) launch_chunk_kernel<T, R, STAGED, true, true>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
+        else launch_chunk_kernel<T, R, STAGED, false, true>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
+    } else {
+        if (has_p) launch_chunk_kernel<T, R, STAGED, true, false>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
+        else launch_chunk_kernel<T, R, STAGED, false, false>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
     }
 }
 
 template <typename R, bool STAGED>
-static void dispatch_chunks(const Category &c, double *stage, bool has_p, bool periodic, int block, hipStream_t s,
-                            const double *xyz, const double *u, const double *p, double nu, double cv, double *rhs) {
+static void dispatch_chunks(const Category &c, double *stage, const ClosureView *cl, bool has_p, bool periodic,
+                            int block, hipStream_t s, const double *xyz, const double *u, const double *p, double nu,
+                            double cv, double *rhs) {
     ChunkView v{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_fslot, c.d_lg, c.d_lf, c.d_delta, stage,
                 (int32_t)c.n};
     const size_t shm = sizeof(double) * (size_t)c.lds_doubles;
     switch (c.type) {
-    case LESASM_TET04: launch_chunks<LESASM_TET04, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R, STAGED>(v, c.n_chunks, shm, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_TET04: launch_chunks<LESASM_TET04, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
     }
 }
 
@@ -185,6 +213,13 @@ bool mesh_is_staged(const lesasm_mesh *m) {
 // the gather of staged rows on the caller's stream.
 static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
     const bool staged = mesh_is_staged(m);
+    ClosureView clv{};
+    const ClosureView *cl = nullptr;
+    if (m->mlp) {
+        clv = ClosureView{mlp_packed(m->mlp), mlp_bias(m->mlp), std::log(m->delta_ref),
+                          m->fallback_tol * m->fallback_tol, m->d_fallbacks};
+        cl = &clv;
+    }
     LESASM_HIP_TRY(hipEventRecord(m->ev_fork, s));
     int used = 0;
     for (int k = 0; k < kNumCat; ++k) {
@@ -200,11 +235,11 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
         const bool periodic = c.d_lf != c.d_lg;
         const bool f32 = m->precision == LESASM_PREC_FP32;
         if (staged) {
-            if (f32) dispatch_chunks<float, true>(c, m->d_stage, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else dispatch_chunks<double, true>(c, m->d_stage, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            if (f32) dispatch_chunks<float, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else dispatch_chunks<double, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
         } else {
-            if (f32) dispatch_chunks<float, false>(c, nullptr, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else dispatch_chunks<double, false>(c, nullptr, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            if (f32) dispatch_chunks<float, false>(c, nullptr, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
         }
     }
     for (int i = 0; i < std::min(used - 1, 3); ++i) {

@@ -85,6 +85,9 @@ struct ChunkView {
 
 constexpr uint32_t kOwnedBit = 0x80000000u;
 
+const short *mlp_packed(const lesasm_mlp *p);
+const float *mlp_bias(const lesasm_mlp *p);
+
 // Shared between translation units.
 int grid_for(size_t n, int block);
 int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, double dt, double *rhs, hipStream_t s,
@@ -135,6 +138,11 @@ struct lesasm_mesh {
     int32_t *d_gslots = nullptr;    // staging rows, in (type, chunk) order
     // side streams and events running the four type kernels concurrently
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    // learned closure (NULL: Vreman)
+    const lesasm_mlp *mlp = nullptr;
+    double delta_ref = 1.0, fallback_tol = 0.05;
+    int chunk_max_nodes = 800;              // node cap of a chunk (LDS budget)
+    unsigned long long *d_fallbacks = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     // profiling: events pending per kernel slot, accumulated times and counts
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[LESASM_NUM_KERNEL_SLOTS];

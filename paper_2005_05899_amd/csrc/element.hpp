@@ -13,6 +13,7 @@
 
 #include "common.hpp"
 #include "refelem.hpp"
+#include "mlp.hpp"
 
 namespace lesasm {
 
@@ -139,6 +140,37 @@ __device__ __forceinline__ R vreman_nut(const R G[3][3], R cd2) {
 // u_g = u0 + sum_a N_a du_a; nu_t; S = G + G^T; C = S u_g + tr(G) u_g;
 // f = w det (C + grad p); T = w (nu + nu_t) S adj^T  (= dV sigma J^-T);
 // acc[a] -= N_a f + T dN_a.
+// Learned-closure context of one wavefront (weights in LDS, private scratch).
+struct MlpCtx {
+    MlpLds w;
+    unsigned char *scratch;
+    float logd;  // log(Delta_e / Delta_ref)
+};
+
+// Subgrid stress of the network minus Vreman's (-nu_t S, S = G + G^T), as the
+// stress-flux tile T'_ik = w sum_j dtau_ij adj_kj of one Gauss point.
+template <typename R>
+__device__ __forceinline__ void mlp_stress_flux(const MlpCtx &mc, const R (&G)[3][3], const R (&S)[3][3], R nut,
+                                                R d2, R adj[3][3], R w, R (&Tp)[3][3]) {
+    float x[kMlpIn], y[kMlpOut];
+    R gn2;
+    mlp_features<R>(G, mc.logd, x, gn2);
+    mlp_wave(mc.w, x, y, mc.scratch);
+    const float tr = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
+    const R sc = d2 * gn2;
+    R dt[3][3];
+    dt[0][0] = sc * (R)(y[0] - tr) + nut * S[0][0];
+    dt[1][1] = sc * (R)(y[1] - tr) + nut * S[1][1];
+    dt[2][2] = sc * (R)(y[2] - tr) + nut * S[2][2];
+    dt[0][1] = dt[1][0] = sc * (R)y[3] + nut * S[0][1];
+    dt[0][2] = dt[2][0] = sc * (R)y[4] + nut * S[0][2];
+    dt[1][2] = dt[2][1] = sc * (R)y[5] + nut * S[1][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Tp[i][k] = w * (dt[i][0] * adj[k][0] + dt[i][1] * adj[k][1] + dt[i][2] * adj[k][2]);
+}
+
 // TET04 is affine: J, G, grad p and nu_t are constant over the element, and
 // the 4-point rule integrates N_a N_b exactly (degree 2), so its quadrature
 // sums collapse to closed forms of the same value:
@@ -146,8 +178,9 @@ __device__ __forceinline__ R vreman_nut(const R G[3][3], R cd2) {
 // With M = S + tr(G) I the EMAC term is C(u) = M u (linear in u), hence
 //   R_a = -det [ M (u_a + sum_b u_b) / 120 + grad p / 24 ] - T dN_a,
 //   T = (1/6) (nu + nu_t) S adj^T,  dN_0 = (-1,-1,-1), dN_a = e_(a-1).
-template <typename R, bool HAS_P>
-__device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> &d, R nu, R cd2, R acc[4][3]) {
+template <typename R, bool HAS_P, bool MLP>
+__device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> &d, R nu, R cd2, R d2, R acc[4][3],
+                                             R dacc[4][3], const MlpCtx *mc) {
     R J[3][3], Gx[3][3], px[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -209,13 +242,26 @@ __device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> 
             acc[a][i] = -(c120 * Cm + c24 * q[i] + visc);
         }
     }
+    if constexpr (MLP) {  // constant gradient: one network evaluation per element
+        R Tp[3][3];
+        mlp_stress_flux<R>(*mc, G, S, nut, d2, adj, (R)(1.0 / 6.0), Tp);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            dacc[0][i] = -(Tp[i][0] + Tp[i][1] + Tp[i][2]);
+#pragma unroll
+            for (int a = 1; a < 4; ++a) dacc[a][i] = Tp[i][a - 1];
+        }
+    }
 }
 
-template <int T, typename R, bool HAS_P>
+// With MLP, dacc receives the residual change from replacing Vreman's stress
+// by the network's: dacc_a = int dN_a/dx_j (tau_mlp - tau_vreman)_ij dV.
+template <int T, typename R, bool HAS_P, bool MLP = false>
 __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R nu, R cd2,
-                                                 R acc[Ref<T>::nn][3]) {
+                                                 R acc[Ref<T>::nn][3], R d2 = (R)0,
+                                                 R (*dacc)[3] = nullptr, const MlpCtx *mc = nullptr) {
     if constexpr (T == LESASM_TET04) {
-        tet_residual<R, HAS_P>(d, nu, cd2, acc);
+        tet_residual<R, HAS_P, MLP>(d, nu, cd2, d2, acc, dacc, mc);
         return;
     }
     using E = Ref<T>;
@@ -223,6 +269,9 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
     const auto &tab = RefConst<T>::tab();
 #pragma unroll
     for (int a = 0; a < nn; ++a) acc[a][0] = acc[a][1] = acc[a][2] = (R)0;
+    if constexpr (MLP)
+#pragma unroll
+        for (int a = 0; a < nn; ++a) dacc[a][0] = dacc[a][1] = dacc[a][2] = (R)0;
 
 #pragma unroll 1
     for (int g = 0; g < E::ng; ++g) {
@@ -313,10 +362,21 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 // a plain store when every element touching it lies in this chunk (owned), an
 // staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
 //   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
-template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
+// Learned closure of a launch: packed weights, filter-width reference and
+// the fallback threshold (squared), plus a counter of Vreman fallbacks.
+struct ClosureView {
+    const short *packed;
+    const float *bias;
+    double log_delta_ref;
+    double tol2;
+    unsigned long long *fallbacks;
+};
+
+template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED, bool MLP = false>
 __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *lds, const double *__restrict__ xyz,
                                            const double *__restrict__ u, const double *__restrict__ p, double nu,
-                                           double cv, double *__restrict__ rhs) {
+                                           double cv, double *__restrict__ rhs, const ClosureView *cl = nullptr,
+                                           int lds_node_doubles = 0) {
     constexpr int nn = Ref<T>::nn;
     const int e0 = c.eoff[j], e1 = c.eoff[j + 1];
     const int g0 = c.goff[j], ng = c.goff[j + 1] - g0;
@@ -338,24 +398,75 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
         sp[k] = HAS_P ? p[f] : 0.0;
         sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
     }
+    if constexpr (MLP) mlp_stage(cl->packed, cl->bias, (unsigned char *)(lds + lds_node_doubles));
     __syncthreads();
 
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        int lg[nn], lf[nn];
+    if constexpr (!MLP) {
+        for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            int lg[nn], lf[nn];
 #pragma unroll
-        for (int a = 0; a < nn; ++a) {
-            lg[a] = c.lg[(size_t)a * c.ld + e];
-            lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+            for (int a = 0; a < nn; ++a) {
+                lg[a] = c.lg[(size_t)a * c.ld + e];
+                lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+            }
+            ElementData<T, R> d;
+            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+            const double dl = c.delta[e];
+            R acc[nn][3];
+            element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
+#pragma unroll
+            for (int a = 0; a < nn; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)acc[a][i]);
         }
-        ElementData<T, R> d;
-        gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
-        const double dl = c.delta[e];
-        R acc[nn][3];
-        element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
+    } else {
+        // Learned closure: whole wavefronts step through the elements together
+        // (the network runs on matrix instructions across all 64 lanes); lanes
+        // past the end repeat the last element and discard it.
+        unsigned char *mlds = (unsigned char *)(lds + lds_node_doubles);
+        MlpCtx mc;
+        mc.w = MlpLds{(const bf16x4_t *)mlds, (const float *)(mlds + kMlpPackedShorts * 2),
+                      (const float *)(mlds + kMlpPackedShorts * 2) + kMlpH,
+                      (const float *)(mlds + kMlpPackedShorts * 2) + 2 * kMlpH};
+        mc.scratch = mlds + kMlpLdsBytes + (threadIdx.x / 64) * kMlpWaveScratch;
+        unsigned fallbacks = 0;
+        const int wave0 = (threadIdx.x / 64) * 64;
+        for (int base = e0; base < e1; base += blockDim.x) {
+            if (base + wave0 >= e1) break;  // whole wavefront past the end (uniform)
+            const bool active = base + (int)threadIdx.x < e1;
+            const int e = active ? base + (int)threadIdx.x : e1 - 1;
+            int lg[nn], lf[nn];
 #pragma unroll
-        for (int a = 0; a < nn; ++a)
+            for (int a = 0; a < nn; ++a) {
+                lg[a] = c.lg[(size_t)a * c.ld + e];
+                lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+            }
+            ElementData<T, R> d;
+            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+            const double dl = c.delta[e];
+            mc.logd = (float)(log(dl) - cl->log_delta_ref);
+            R acc[nn][3], dacc[nn][3];
+            element_residual<T, R, HAS_P, true>(d, (R)nu, (R)(cv * dl * dl), acc, (R)(dl * dl), dacc, &mc);
+            // fallback test: |R_mlp - R_vreman| <= tol |R_vreman| (element 2-norms)
+            R nd = (R)0, na = (R)0;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)acc[a][i]);
+            for (int a = 0; a < nn; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    nd += dacc[a][i] * dacc[a][i];
+                    na += acc[a][i] * acc[a][i];
+                }
+            const bool use_mlp = (double)nd <= cl->tol2 * (double)na;
+            if (active) {
+                fallbacks += !use_mlp;
+#pragma unroll
+                for (int a = 0; a < nn; ++a)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)(use_mlp ? acc[a][i] + dacc[a][i] : acc[a][i]));
+            }
+        }
+        if (fallbacks) atomicAdd(cl->fallbacks, (unsigned long long)fallbacks);
     }
     __syncthreads();
 

@@ -190,10 +190,10 @@ template <class T> static void dfree(lesasm_mesh *m, T *&p) {
 
 // Chunks for the chunked scatter of category k: runs of consecutive internal
 // elements, at most m->chunk_elems long and with at most kChunkMaxNodes
-// distinct geometry and field nodes, so a chunk's node data fits in LDS.  Node
+// distinct geometry and field nodes (m->chunk_max_nodes: 800, or 400 when the
+// learned closure also needs LDS), so a chunk's node data fits in LDS.  Node
 // lists are sorted ascending (coalesced loads); a field node is owned by a
 // chunk when all of its incidences in the mesh lie in that chunk.
-constexpr int kChunkMaxNodes = 800;
 
 static int chunk_length(const lesasm_mesh *m, int64_t n) {
     if (m->chunk_elems) return m->chunk_elems;
@@ -239,7 +239,8 @@ static int build_chunks(lesasm_mesh *m, int k) {
                 newg += gslot[cg[(size_t)a * n + e]] < 0;
                 newf += fslot[cf[(size_t)a * n + e]] < 0;
             }
-            if (e > start && ((int)gl.size() + newg > kChunkMaxNodes || (int)fl.size() + newf > kChunkMaxNodes)) break;
+            if (e > start && ((int)gl.size() + newg > m->chunk_max_nodes || (int)fl.size() + newf > m->chunk_max_nodes))
+                break;
             for (int a = 0; a < nnode; ++a) {
                 const int32_t g = cg[(size_t)a * n + e], f = cf[(size_t)a * n + e];
                 if (gslot[g] < 0) { gslot[g] = 0; gl.push_back(g); }
@@ -709,4 +710,41 @@ extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t 
     case LESASM_OPT_CHUNK: *value = m->chunk_elems; return LESASM_OK;
     default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
     }
+}
+
+extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, double delta_ref, double fallback_tol) {
+    if (!m) return fail(LESASM_E_INVALID_ARG, "set_closure: mesh is NULL");
+    if (mlp && (!(delta_ref > 0.0) || !(fallback_tol >= 0.0)))
+        return fail(LESASM_E_INVALID_ARG, "set_closure: need delta_ref > 0 and fallback_tol >= 0");
+    if (mlp && !is_chunked(m)) return fail(LESASM_E_UNSUPPORTED, "set_closure: needs a chunked scatter");
+    int cur = 0;
+    LESASM_HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) return fail(LESASM_E_STATE, "set_closure: current device differs from the mesh's device");
+    LESASM_HIP_TRY(hipDeviceSynchronize());
+    if (mlp && !m->d_fallbacks) {
+        int st = dalloc(m, &m->d_fallbacks, 1);
+        if (st) return st;
+        LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long)));
+    }
+    m->mlp = mlp;
+    m->delta_ref = mlp ? delta_ref : 1.0;
+    m->fallback_tol = mlp ? fallback_tol : 0.05;
+    const int cap = mlp ? 400 : 800;
+    if (cap != m->chunk_max_nodes) {
+        m->chunk_max_nodes = cap;
+        return build_scatter(m);
+    }
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_closure_fallbacks(lesasm_mesh *m, uint64_t *count) {
+    if (!m || !count) return fail(LESASM_E_INVALID_ARG, "closure_fallbacks: NULL argument");
+    *count = 0;
+    if (!m->d_fallbacks) return LESASM_OK;
+    unsigned long long v = 0, zero = 0;
+    LESASM_HIP_TRY(hipDeviceSynchronize());
+    LESASM_HIP_TRY(hipMemcpy(&v, m->d_fallbacks, sizeof(v), hipMemcpyDeviceToHost));
+    LESASM_HIP_TRY(hipMemcpy(m->d_fallbacks, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    *count = v;
+    return LESASM_OK;
 }

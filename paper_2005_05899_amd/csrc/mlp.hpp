@@ -1,0 +1,158 @@
+// Learned subgrid closure: a 10-64-64-6 perceptron evaluated by one wavefront
+// for 64 samples at once with BF16 matrix-core instructions (FP32 sums).
+//
+// The chain is computed transposed, H^T = W^T X^T, so that a layer's 16x16
+// accumulator tiles are, element for element, the B operand of the next
+// layer (rows = hidden units = the K index, columns = samples):
+//   v_mfma_f32_16x16x16_bf16:  A[i][k] in lane i + 16 (k/4), slot k%4
+//                              B[k][j] in lane j + 16 (k/4), slot k%4
+//                              D[i][j] in lane j + 16 (i/4), slot i%4
+// Weights are packed once into those A tiles (W1^T: 4 row tiles, K padded
+// from 10 to 16; W2^T: 4 x 4 tiles; W3^T: 1 row tile, 6 of 16 rows used).
+// Inputs:  x = [G / |G|_F (9), log(Delta / Delta_ref)], outputs 6 symmetric
+// components (xx, yy, zz, xy, xz, yz) before the trace removal.
+#pragma once
+
+#include "common.hpp"
+
+namespace lesasm {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMlpIn = 10, kMlpH = 64, kMlpOut = 6;
+constexpr int kMlpParams = kMlpIn * kMlpH + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH * kMlpOut + kMlpOut;  // 5254
+// packed A tiles: 4 (W1) + 16 (W2) + 4 (W3), each 64 lanes x 4 bf16
+constexpr int kMlpTiles = 4 + 16 + 4;
+constexpr int kMlpPackedShorts = kMlpTiles * 64 * 4;
+// LDS bytes of the packed weights and biases (b1, b2, b3 padded to 8)
+constexpr int kMlpLdsBytes = kMlpPackedShorts * 2 + (kMlpH + kMlpH + 8) * 4;
+// per-wavefront LDS scratch: 64 samples x 16 bf16 inputs, then 64 x 8 floats outputs
+constexpr int kMlpWaveScratch = 64 * 16 * 2 + 64 * 8 * 4;
+
+// Round-to-nearest-even float -> bf16 bits (finite inputs).
+__device__ __forceinline__ short f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+struct MlpLds {
+    const bf16x4_t *tiles;  // [kMlpTiles][64]
+    const float *b1, *b2, *b3;
+};
+
+// Copy packed weights (global, bf16 tiles + f32 biases) into LDS; call with the
+// whole workgroup, followed by a barrier.
+__device__ __forceinline__ MlpLds mlp_stage(const short *__restrict__ packed, const float *__restrict__ bias,
+                                            unsigned char *lds) {
+    short *t = (short *)lds;
+    for (int k = threadIdx.x; k < kMlpPackedShorts / 4; k += blockDim.x)
+        ((bf16x4_t *)t)[k] = ((const bf16x4_t *)packed)[k];
+    float *b = (float *)(lds + kMlpPackedShorts * 2);
+    for (int k = threadIdx.x; k < kMlpH + kMlpH + 8; k += blockDim.x) b[k] = bias[k];
+    return MlpLds{(const bf16x4_t *)t, b, b + kMlpH, b + 2 * kMlpH};
+}
+
+// Whole-wavefront evaluation: every lane supplies the 10 inputs of its own
+// sample and receives its 6 outputs.  All 64 lanes must call it together
+// (matrix instructions ignore the execution mask).  scratch: kMlpWaveScratch
+// bytes of LDS private to this wavefront.
+__device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpIn], float (&y)[kMlpOut],
+                                         unsigned char *scratch) {
+    const int lane = __lane_id();
+    const int lq = lane >> 4, lr = lane & 15;
+    short *xs = (short *)scratch;                 // [64][16]
+    float *ys = (float *)(scratch + 64 * 16 * 2);  // [64][8]
+    {
+        bf16x4_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * q + t;
+                v[q][t] = k < kMlpIn ? f2bf(x[k]) : (short)0;
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ((bf16x4_t *)(xs + 16 * lane))[q] = v[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // B operands of layer 1: X^T[k][sample], sample = 16 nt + lr, k = 4 lq + t
+    bf16x4_t bx[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bx[nt] = ((const bf16x4_t *)(xs + 16 * (16 * nt + lr)))[lq];
+
+    // layer 1: H1^T = relu(W1^T X^T + b1), 4 row tiles x 4 sample tiles
+    bf16x4_t h1[4][4];  // [k-step = row tile][sample tile]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const bf16x4_t a = w.tiles[mt * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bx[nt], acc, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float v = acc[t] + w.b1[16 * mt + 4 * lq + t];
+                h1[mt][nt][t] = f2bf(v > 0.f ? v : 0.f);
+            }
+        }
+    }
+    // layer 2: H2^T = relu(W2^T H1^T + b2)
+    bf16x4_t h2[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4_t acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x4_t a = w.tiles[(4 + 4 * mt + ks) * 64 + lane];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[ks][nt], acc[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float v = acc[nt][t] + w.b2[16 * mt + 4 * lq + t];
+                h2[mt][nt][t] = f2bf(v > 0.f ? v : 0.f);
+            }
+    }
+    // layer 3: Y^T = W3^T H2^T + b3 (rows 0..5 of one tile)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w.tiles[(20 + ks) * 64 + lane], h2[ks][nt], acc, 0, 0, 0);
+        if (lq < 2)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) ys[8 * (16 * nt + lr) + 4 * lq + t] = acc[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) y[o] = ys[8 * lane + o] + w.b3[o];
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Inputs of one Gauss point: G (row-major du_i/dx_j) and log(Delta/Delta_ref).
+template <typename R>
+__device__ __forceinline__ void mlp_features(const R (&G)[3][3], float logd, float (&x)[kMlpIn], R &gnorm2) {
+    gnorm2 = (R)0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gnorm2 += G[i][j] * G[i][j];
+    const float inv = gnorm2 > (R)0 ? __builtin_amdgcn_rsqf((float)gnorm2) : 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) x[3 * i + j] = (float)G[i][j] * inv;
+    x[9] = logd;
+}
+
+}  // namespace lesasm

@@ -33,8 +33,11 @@ EXPORTS = [
     "lesasm_stepper_rk3_stages", "lesasm_pressure_solve", "lesasm_stepper_stats", "lesasm_stepper_laplacian",
     "lesasm_batch_create", "lesasm_batch_destroy", "lesasm_batch_configure", "lesasm_batch_get_config",
     "lesasm_batch_assemble", "lesasm_batch_tune", "lesasm_batch_rk3_graph", "lesasm_batch_rk3_launch",
-    "lesasm_batch_rk3_eager",
+    "lesasm_batch_rk3_eager", "lesasm_mlp_create", "lesasm_mlp_destroy", "lesasm_mlp_get_params",
+    "lesasm_mlp_set_params", "lesasm_mlp_loss_grad", "lesasm_mlp_adam", "lesasm_mlp_train_step", "lesasm_mlp_commit",
+    "lesasm_mlp_forward_f32", "lesasm_mlp_infer_bf16", "lesasm_mesh_set_closure", "lesasm_mesh_closure_fallbacks",
 ]
+MLP_PARAMS = 5254
 ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
 
 
@@ -88,6 +91,11 @@ def load(path: str = LIB_PATH):
         "lesasm_batch_get_config": [P, P, P, P, P], "lesasm_batch_assemble": [P, P, P, P, P, P],
         "lesasm_batch_tune": [P, P, P, P, P, ctypes.c_char_p, I, P], "lesasm_batch_rk3_graph": [P, P, P, P, D, P],
         "lesasm_batch_rk3_launch": [P, P], "lesasm_batch_rk3_eager": [P, P, P, P, D, P],
+        "lesasm_mlp_create": [P, P], "lesasm_mlp_destroy": [P], "lesasm_mlp_get_params": [P, P],
+        "lesasm_mlp_set_params": [P, P], "lesasm_mlp_loss_grad": [P, P, P, I, P, P, P],
+        "lesasm_mlp_adam": [P, P, ctypes.c_float, P], "lesasm_mlp_train_step": [P, P, P, I, ctypes.c_float, P, P],
+        "lesasm_mlp_commit": [P], "lesasm_mlp_forward_f32": [P, P, I, P, P], "lesasm_mlp_infer_bf16": [P, P, I, P, P],
+        "lesasm_mesh_set_closure": [P, P, D, D], "lesasm_mesh_closure_fallbacks": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -372,3 +380,82 @@ class Batch:
     def rk3_eager(self, us, ps, nus, dt: float):
         u, p, nu = self._args(us, ps, nus)
         check(load().lesasm_batch_rk3_eager(self._h, u, p, nu, float(dt), _stream()))
+
+
+class MLP:
+    """The learned subgrid closure network on the GPU (lesasm_mlp_*)."""
+
+    def __init__(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        h = ctypes.c_void_p()
+        check(load().lesasm_mlp_create(p.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lesasm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, np.float32)
+        check(load().lesasm_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, np.float32)
+        check(load().lesasm_mlp_set_params(self._h, p.ctypes.data))
+
+    @staticmethod
+    def _f32(t, cols):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 2 and t.shape[1] == cols):
+            raise ValueError(f"expected a contiguous float32 [n, {cols}] GPU tensor")
+        return t
+
+    def loss_grad(self, x, t):
+        self._f32(x, 10), self._f32(t, 6)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        check(load().lesasm_mlp_loss_grad(self._h, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream()))
+        return loss, g
+
+    def adam(self, grad=None, lr: float = 1e-3):
+        check(load().lesasm_mlp_adam(self._h, _ptr(grad), ctypes.c_float(lr), _stream()))
+
+    def train_step(self, x, t, lr: float = 1e-3, loss=None):
+        self._f32(x, 10), self._f32(t, 6)
+        check(load().lesasm_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], ctypes.c_float(lr), _ptr(loss),
+                                           _stream()))
+
+    def commit(self):
+        check(load().lesasm_mlp_commit(self._h))
+
+    def forward_f32(self, x):
+        self._f32(x, 10)
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+        check(load().lesasm_mlp_forward_f32(self._h, _ptr(x), x.shape[0], _ptr(y), _stream()))
+        return y
+
+    def infer_bf16(self, x):
+        self._f32(x, 10)
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+        check(load().lesasm_mlp_infer_bf16(self._h, _ptr(x), x.shape[0], _ptr(y), _stream()))
+        return y
+
+
+def set_closure(mesh: Mesh, mlp: "MLP | None", delta_ref: float = 1.0, fallback_tol: float = 0.05):
+    check(load().lesasm_mesh_set_closure(mesh._h, None if mlp is None else mlp._h, float(delta_ref),
+                                         float(fallback_tol)))
+
+
+def closure_fallbacks(mesh: Mesh) -> int:
+    v = ctypes.c_uint64()
+    check(load().lesasm_mesh_closure_fallbacks(mesh._h, ctypes.byref(v)))
+    return v.value
