@@ -359,6 +359,25 @@ def random_fourier_velocity(n_modes: int = 512, kmax: int = 16, urms: float = 1.
     return FourierField(k, a, phase)
 
 
+def random_fourier_velocity_peaked(kpeak: float = 4.0, kmax: int = 10, n_modes: int = 512, urms: float = 1.0,
+                                   seed: int = 7) -> FourierField:
+    """Divergence-free random Fourier field whose shell energy peaks near
+    kpeak: mode amplitudes |k| (|k|/kpeak)^2 exp(-(|k|/kpeak)^2) / |k|^2 over
+    integer modes uniform in the ball 1 <= |k| <= kmax (initial condition of
+    the decaying-turbulence runs)."""
+    rng = np.random.default_rng(seed)
+    k = _integer_modes(n_modes, kmax, rng)
+    kn = np.linalg.norm(k, axis=1)
+    g = rng.standard_normal(k.shape)
+    d = g - ((g * k).sum(axis=1) / kn ** 2)[:, None] * k
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    amp = (kn / kpeak) ** 2 * np.exp(-(kn / kpeak) ** 2) / kn
+    a = d * amp[:, None]
+    phase = rng.uniform(0.0, 2 * math.pi, len(k))
+    a *= urms / math.sqrt(0.5 * (a * a).sum() / 3.0)
+    return FourierField(k, a, phase)
+
+
 def random_fourier_scalar(n_modes: int = 128, kmax: int = 8, rms: float = 0.5, seed: int = 11,
                           slope: float = -11.0 / 6.0) -> FourierField:
     """Smooth seeded scalar field (used as a pressure input), rms value ``rms``."""
