@@ -426,7 +426,8 @@ def periodic_tg_case(n: int = 16, noise: float = 1e-3, nu: float = 1e-5, c: floa
 
 
 def hybrid_case(target_elems: int, seed_mesh: int = 2, seed_u: int = 3, seed_p: int = 11,
-                nu: float = 1.5e-5, c: float = 0.1, n_xy: int | None = None, with_p: bool = True) -> Case:
+                nu: float = 1.5e-5, c: float = 0.1, n_xy: int | None = None, with_p: bool = True,
+                n_modes: int = 512) -> Case:
     """Graded, perturbed hybrid box with about ``target_elems`` elements
     (40 % TET04, 40 % PEN06, 5 % PYR05, 15 % HEX08), divergence-free random
     Fourier velocity (512 modes, |k| <= 16, u_rms 1) and a smooth pressure."""
@@ -437,7 +438,7 @@ def hybrid_case(target_elems: int, seed_mesh: int = 2, seed_u: int = 3, seed_p: 
     layers = hybrid_layers(n_xy * n_xy, target_elems)
     mesh = hybrid_box(n_xy, n_xy, layers, seed=seed_mesh)
     xf = mesh.field_coords()
-    u = random_fourier_velocity(seed=seed_u)(xf)
+    u = random_fourier_velocity(n_modes=n_modes, seed=seed_u)(xf)
     p = random_fourier_scalar(seed=seed_p)(xf)[:, 0] if with_p else None
     return Case(f"hybrid_{mesh.n_elems}", mesh, u, p, nu, c,
                 meta={"seed_mesh": seed_mesh, "seed_u": seed_u, "seed_p": seed_p, "n_xy": n_xy})
