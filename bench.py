@@ -10,7 +10,8 @@ Beside the FP64 value the line carries the mixed-precision form (FP32 element
 contractions) and, if trained weights are present, the learned closure, each
 with its error against the FP64 CPU oracle on the same inputs.  The batched
 workload (64 partitions, about 25 M elements, persistent launch) is a separate
-mode: --workload batch64.
+mode: --workload batch64; the 20 M-element precision comparison (FP32
+contractions and a full time step in both precisions) is --workload precision20m.
 """
 from __future__ import annotations
 
@@ -304,12 +305,100 @@ def run_batch(args):
         mesh.close()
 
 
+def run_precision(args):
+    """The 20 M-element hybrid box (205 x 205 cells): FP64 and FP32-contraction
+    assemblies, each against the FP64 oracle field by field; one full time step
+    (three Runge-Kutta stages and the FP64 pressure projection) in both
+    precisions; the learned closure if trained weights are present."""
+    import torch
+    import oracle
+    from paper_2005_05899_amd import lesasm, meshgen
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    case = meshgen.hybrid_20m_case()
+    m = case.mesh
+    print(f"  20M case generated: {m.n_elems} elements ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
+    mesh = lesasm.Mesh.from_arrays(m, case.vreman_c)
+    u = mesh.to_internal(torch.from_numpy(case.u).cuda())
+    p = mesh.to_internal(torch.from_numpy(case.p).cuda())
+    E = m.n_elems
+    res = {}
+    for prec in ("fp64", "fp32"):
+        mesh.precision = prec
+        el, kt, r = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
+        res[prec] = {"value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                     "rhs": mesh.to_user(r).cpu().numpy()}
+        print(f"  {prec}: {res[prec]['ms_per_step']:.3f} ms per assembly", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    ref = oracle.assemble(m, case.u, case.p, case.nu, case.vreman_c)
+    t_oracle = time.perf_counter() - t1
+    print(f"  oracle: {t_oracle:.1f} s", file=sys.stderr, flush=True)
+    for prec in res:
+        res[prec]["error_vs_fp64_oracle"] = field_errors(res[prec].pop("rhs"), ref)
+
+    # one full step from the same state in both precisions
+    dt = 1e-3
+    step = {}
+    for prec in ("fp64", "fp32"):
+        mesh.precision = prec
+        st = lesasm.Stepper(mesh, case.nu, dt, rtol=1e-10, maxit=20000)
+        uu, pp = u.clone(), p.clone()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st.step(uu, pp)
+        torch.cuda.synchronize()
+        it, rr = st.stats()
+        step[prec] = {"ms": 1e3 * (time.perf_counter() - ts), "cg_iterations": it, "cg_relative_residual": rr,
+                      "u": uu, "p": pp}
+        st.close()
+        print(f"  step {prec}: {step[prec]['ms']:.1f} ms, {it} CG iterations", file=sys.stderr, flush=True)
+    du64 = mesh.to_user(step["fp64"]["u"] - u).cpu().numpy()
+    du32 = mesh.to_user(step["fp32"]["u"] - u).cpu().numpy()
+    u64 = mesh.to_user(step["fp64"]["u"]).cpu().numpy()
+    u32 = mesh.to_user(step["fp32"]["u"]).cpu().numpy()
+    for prec in step:
+        del step[prec]["u"], step[prec]["p"]
+    step_cmp = {"velocity_fp32_vs_fp64": field_errors(u32, u64),
+                "increment_fp32_vs_fp64": field_errors(du32, du64), "dt": dt}
+
+    variants = {}
+    if os.path.exists(WEIGHTS):
+        params = np.load(WEIGHTS)
+        meta = json.load(open(WEIGHTS_META)) if os.path.exists(WEIGHTS_META) else {}
+        net = lesasm.MLP(params)
+        for prec in ("fp32", "fp64"):
+            mesh.precision = prec
+            lesasm.set_closure(mesh, net, meta.get("delta_ref", 0.1), 0.05)
+            lesasm.closure_fallbacks(mesh)
+            el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
+            fb = lesasm.closure_fallbacks(mesh)
+            variants[f"learned_closure_{prec}"] = {
+                "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                "fallback_fraction": fb / (E * (args.steps + args.warmup)),
+                "difference_vs_fp64_vreman_oracle": field_errors(mesh.to_user(rl).cpu().numpy(), ref)}
+            lesasm.set_closure(mesh, None)
+        net.close()
+    out = {
+        "metric": "element-assemblies/s + % HBM peak; mixed/learned vs FP64 at stated error",
+        "value": res["fp64"]["value"], "unit": "element-assemblies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["fp64"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded hybrid mesh and random Fourier fields)",
+        "config": {"workload": "hybrid box, 20M elements (205 x 205 cells), precision comparison",
+                   "elements": E, "field_nodes": m.n_field_nodes, "seeds": case.meta},
+        "precisions": res, "full_step": step, "full_step_comparison": step_cmp, "variants": variants,
+        "oracle_seconds_single_thread": t_oracle,
+    }
+    print(json.dumps(out), flush=True)
+    mesh.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["hybrid2m", "batch64"], default="hybrid2m")
+    ap.add_argument("--workload", choices=["hybrid2m", "batch64", "precision20m"], default="hybrid2m")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--scatter", choices=["staged", "chunk_atomic", "colour", "direct"], default="staged")
     ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatters)")
@@ -322,6 +411,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         run_batch(args)
+    elif args.workload == "precision20m":
+        run_precision(args)
     else:
         run_main(args)
 
