@@ -79,8 +79,12 @@ def field_errors(got, ref) -> dict:
     return out
 
 
-def time_assembly(torch, mesh, u, p, nu, steps, warmup):
+def time_assembly(torch, mesh, u, p, nu, steps, warmup, concurrent=True):
+    """Wall time of `steps` assemblies between two synchronisations, and the
+    per-kernel HIP-event durations of the same launches.  concurrent=False
+    runs the element-type kernels one after another (isolated durations)."""
     from paper_2005_05899_amd import lesasm
+    mesh.set_option(lesasm.OPT_CONCURRENT, 1 if concurrent else 0)
     rhs = torch.empty_like(u)
     for _ in range(warmup):
         mesh.assemble_momentum_rhs(u, p, nu, out=rhs)
@@ -95,6 +99,7 @@ def time_assembly(torch, mesh, u, p, nu, steps, warmup):
     elapsed = time.perf_counter() - t0
     kt = mesh.kernel_times(reset=True)
     mesh.set_option(lesasm.OPT_PROFILE, 0)
+    mesh.set_option(lesasm.OPT_CONCURRENT, 1)
     return elapsed, kt, rhs
 
 
@@ -141,25 +146,37 @@ def run_main(args):
     p = mesh.to_internal(torch.from_numpy(case.p).cuda())
     torch.cuda.synchronize()
 
-    elapsed, kt, rhs = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
+    # the timed region: the whole assembly as a caller runs it (element-type
+    # kernels concurrent unless --isolated)
+    elapsed, kt_conc, rhs = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup,
+                                          concurrent=not args.isolated)
+    # the same launches one kernel at a time: isolated durations for the roofline
+    el_iso, kt, _ = time_assembly(torch, mesh, u, p, case.nu, args.steps, 2, concurrent=False)
     E = m.n_elems
     value = E * args.steps / elapsed
-    per_kernel = {}
-    for t, slot in SLOT.items():
-        ms, n = kt[slot]
-        if n:
-            avg = ms / n
-            fl = FLOPS_PER_ELEMENT[t] * mesh.n_per_type[t]
-            per_kernel[slot] = {"avg_ms": avg, "launches": n, "elements": mesh.n_per_type[t],
-                                "algorithmic_tflops": fl / (avg * 1e-3) / 1e12,
-                                "algorithmic_GBs": per_type_bytes(m, t) / (avg * 1e-3) / 1e9}
-    for extra in ("gather", "fill"):
-        ms, n = kt[extra]
-        if n:
-            per_kernel[extra] = {"avg_ms": ms / n, "launches": n}
+    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+
+    def kernel_table(kt):
+        table = {}
+        for t, slot in SLOT.items():
+            ms, n = kt[slot]
+            if n:
+                avg = ms / n
+                fl = FLOPS_PER_ELEMENT[t] * mesh.n_per_type[t]
+                table[slot] = {"avg_ms": avg, "launches": n, "elements": mesh.n_per_type[t],
+                               "algorithmic_tflops": fl / (avg * 1e-3) / 1e12,
+                               "frac_of_peak": fl / (avg * 1e-3) / 1e12 / peak,
+                               "algorithmic_GBs": per_type_bytes(m, t) / (avg * 1e-3) / 1e9}
+        for extra in ("gather", "fill"):
+            ms, n = kt[extra]
+            if n:
+                table[extra] = {"avg_ms": ms / n, "launches": n}
+        return table
+
+    per_kernel = kernel_table(kt)
+    per_kernel_conc = kernel_table(kt_conc)
     dominant = max((k for k in per_kernel if k in SLOT.values()), key=lambda k: per_kernel[k]["avg_ms"])
     dk = per_kernel[dominant]
-    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     ab = algorithmic_bytes(m, True)
     step_s = elapsed / args.steps
     total_flops = sum(FLOPS_PER_ELEMENT[t] * mesh.n_per_type[t] for t in SLOT)
@@ -182,7 +199,7 @@ def run_main(args):
                    "elements": E, "field_nodes": m.n_field_nodes,
                    "per_type": {SLOT[t]: mesh.n_per_type[t] for t in SLOT},
                    "nu": case.nu, "vreman_c": case.vreman_c, "seeds": case.meta},
-        "roofline": {"bound": "alu", "kernel": f"k_assemble_chunk<{dominant}>",
+        "roofline": {"bound": "alu", "kernel": f"k_assemble_chunk<{dominant}> (isolated launches)",
                      "achieved": dk["algorithmic_tflops"], "peak": peak, "unit": "TFLOP/s",
                      "frac": dk["algorithmic_tflops"] / peak,
                      "traffic": None if traffic is None else traffic["bytes_per_launch"]},
@@ -190,7 +207,9 @@ def run_main(args):
                 "frac_of_peak": ab / step_s / 1e9 / HBM_PEAK_GBS},
         "assembly": {"algorithmic_tflops": total_flops / step_s / 1e12,
                      "frac_of_peak": total_flops / step_s / 1e12 / peak},
-        "kernels": per_kernel,
+        "kernels_isolated": per_kernel,
+        "kernels_concurrent": per_kernel_conc,
+        "isolated_ms_per_step": 1e3 * el_iso / args.steps,
         "source_hash": source_hash(),
     }
     if args.variants:
@@ -393,17 +412,45 @@ def run_precision(args):
     mesh.close()
 
 
+def run_copy(args):
+    """A plain device copy of 512 MiB per step: the calibration workload for
+    the hardware byte counters (FETCH_SIZE and WRITE_SIZE should read 512 MiB
+    each per copy)."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 64 << 20  # doubles: 512 MiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nbytes = 2 * 8 * n
+    print(json.dumps({"metric": "device copy bandwidth (counter calibration)", "value": nbytes * args.steps / el / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "copy of 512 MiB (read 512 MiB, write 512 MiB per step)",
+                                 "bytes_read_per_step": 8 * n, "bytes_written_per_step": 8 * n}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["hybrid2m", "batch64", "precision20m"], default="hybrid2m")
+    ap.add_argument("--workload", choices=["hybrid2m", "batch64", "precision20m", "copy"], default="hybrid2m")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--scatter", choices=["staged", "chunk_atomic", "colour", "direct"], default="staged")
     ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatters)")
     ap.add_argument("--no-variants", dest="variants", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--isolated", action="store_true",
+                    help="run the element-type kernels one after another in the timed region too")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the assembly of one mesh "
@@ -413,6 +460,8 @@ def main():
         run_batch(args)
     elif args.workload == "precision20m":
         run_precision(args)
+    elif args.workload == "copy":
+        run_copy(args)
     else:
         run_main(args)
 

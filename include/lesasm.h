@@ -158,10 +158,14 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
 #define LESASM_OPT_CHUNK 6        /* elements per chunk of the chunked scatters, 32..4096, or 0
                                      (default) for min(512, max(64, 2^floor(log2(n_type/256)))) per
                                      type; setting it rebuilds the chunks (synchronises) */
+#define LESASM_OPT_CONCURRENT 7   /* 1 (default): the element-type kernels of one chunked assembly run
+                                     concurrently on forked streams (joined before return); 0: one
+                                     after another on the caller's stream (isolated kernel timings) */
 
 #define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
-#define LESASM_PREC_FP32 1 /* element contractions in FP32 on origin- and mean-shifted
-                              data; gather, nodal accumulation and output stay FP64 */
+#define LESASM_PREC_FP32 1 /* element contractions in FP32 on coefficients formed in FP64
+                              (modal coefficients, or node-0-shifted values for TET04);
+                              gather, nodal accumulation and output stay FP64 */
 #define LESASM_RHS_RESIDUAL 0  /* d_rhs = rhs (right-hand side of M_L du/dt = rhs) */
 #define LESASM_RHS_INCREMENT 1 /* d_rhs = dt * M_L^{-1} rhs */
 

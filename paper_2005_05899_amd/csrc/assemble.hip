@@ -226,7 +226,7 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
         const Category &c = m->cat[k];
         if (c.n == 0) continue;
         hipStream_t sk = s;
-        if (used > 0) {
+        if (used > 0 && m->concurrent) {
             sk = m->side[(used - 1) % 3];
             if (used <= 3) LESASM_HIP_TRY(hipStreamWaitEvent(sk, m->ev_fork, 0));
         }
@@ -242,7 +242,7 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
             else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
         }
     }
-    for (int i = 0; i < std::min(used - 1, 3); ++i) {
+    for (int i = 0; i < (m->concurrent ? std::min(used - 1, 3) : 0); ++i) {
         LESASM_HIP_TRY(hipEventRecord(m->ev_join[i], m->side[i]));
         LESASM_HIP_TRY(hipStreamWaitEvent(s, m->ev_join[i], 0));
     }

@@ -126,6 +126,7 @@ struct lesasm_mesh {
     int check_finite = 0;
     int block = 256;
     int profile = 0;
+    int concurrent = 1;  // element-type kernels on forked streams
     int chunk_elems = 0;            // elements per chunk of the chunked scatter (0: per-type heuristic)
     std::vector<int32_t> h_finc;    // incidences per internal field node (all types)
     // staged scatter: shared nodes get one staging row per chunk touching them;

@@ -5,15 +5,16 @@
 // One thread owns one element; its node data and residual live in registers.
 // Loops over nodes are unrolled; the Gauss-point loop is not (tables come from
 // constant memory through scalar loads), so only one point's temporaries are
-// live at a time.  Coordinates, velocities and pressures are shifted by the
-// values at local node 0 (in FP64) before the contraction precision R is
-// applied: gradients are unchanged (the reference derivatives sum to zero)
-// and in FP32 the shift removes the cancellation of absolute coordinates.
+// live at a time.  Node data enter as FP64 and are turned into modal
+// coefficients (PYR05, PEN06, HEX08) or node-0-shifted values (TET04) before
+// the contraction precision R is applied, so that in FP32 no absolute
+// coordinate is ever subtracted.
 #pragma once
 
 #include "common.hpp"
 #include "refelem.hpp"
 #include "mlp.hpp"
+#include "modal.hpp"
 
 namespace lesasm {
 
@@ -27,14 +28,75 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + slot;
 }
 
+// Element data in registers.  PYR05, PEN06 and HEX08 hold the modal
+// coefficients of coordinates, velocity and pressure (modal.hpp); the affine
+// TET04 holds node values shifted by local node 0 (in FP64, before the
+// contraction precision R is applied), since its closed form works on nodes.
 template <int T, typename R> struct ElementData {
-    static constexpr int nn = Ref<T>::nn;
-    int fid[nn];        // field node ids (scatter targets)
-    R x[nn][3];         // coordinates relative to node 0
-    R du[nn][3];        // velocity relative to node 0
-    R dp[nn];           // pressure relative to node 0
-    double u0[3];       // velocity at node 0
+    static constexpr int nn = Ref<T>::nn, nm = Modal<T>::nm;
+    int fid[nn];    // field node ids (scatter targets)
+    R X[3][nm];     // coordinate coefficients (X[i][0], the mean, is unused)
+    R U[3][nm];     // velocity coefficients
+    R P[nm];        // pressure coefficients (P[0] unused)
 };
+
+template <typename R> struct ElementData<LESASM_TET04, R> {
+    static constexpr int nn = 4;
+    int fid[nn];
+    R x[nn][3];     // coordinates relative to node 0
+    R du[nn][3];    // velocity relative to node 0
+    R dp[nn];       // pressure relative to node 0
+    double u0[3];   // velocity at node 0
+};
+
+// Fill d from FP64 node values given by accessors xa(a, k), ua(a, k), pa(a).
+template <int T, typename R, bool HAS_P, class XA, class UA, class PA>
+__device__ __forceinline__ void load_element(ElementData<T, R> &d, XA xa, UA ua, PA pa) {
+    constexpr int nn = Ref<T>::nn;
+    if constexpr (T == LESASM_TET04) {
+        double x0[3], p0 = HAS_P ? pa(0) : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            x0[k] = xa(0, k);
+            d.u0[k] = ua(0, k);
+        }
+#pragma unroll
+        for (int a = 0; a < nn; ++a) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                d.x[a][k] = a ? (R)(xa(a, k) - x0[k]) : (R)0;
+                d.du[a][k] = a ? (R)(ua(a, k) - d.u0[k]) : (R)0;
+            }
+            d.dp[a] = (HAS_P && a) ? (R)(pa(a) - p0) : (R)0;
+        }
+    } else {
+        using M = Modal<T>;
+        double v[nn], c[nn];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int a = 0; a < nn; ++a) v[a] = xa(a, k);
+            M::to_modal(v, c);
+#pragma unroll
+            for (int m = 0; m < nn; ++m) d.X[k][m] = (R)c[m];
+#pragma unroll
+            for (int a = 0; a < nn; ++a) v[a] = ua(a, k);
+            M::to_modal(v, c);
+#pragma unroll
+            for (int m = 0; m < nn; ++m) d.U[k][m] = (R)c[m];
+        }
+        if constexpr (HAS_P) {
+#pragma unroll
+            for (int a = 0; a < nn; ++a) v[a] = pa(a);
+            M::to_modal(v, c);
+#pragma unroll
+            for (int m = 0; m < nn; ++m) d.P[m] = (R)c[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < nn; ++m) d.P[m] = (R)0;
+        }
+    }
+}
 
 template <int T, typename R, bool HAS_P>
 __device__ __forceinline__ void gather(ElementData<T, R> &d, const CatView &c, int e,
@@ -47,22 +109,9 @@ __device__ __forceinline__ void gather(ElementData<T, R> &d, const CatView &c, i
         gid[a] = c.cg[(size_t)a * c.ld + e];
         d.fid[a] = (c.cf == c.cg) ? gid[a] : c.cf[(size_t)a * c.ld + e];
     }
-    double x0[3], p0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        x0[k] = xyz[3 * (size_t)gid[0] + k];
-        d.u0[k] = u[3 * (size_t)d.fid[0] + k];
-    }
-    if (HAS_P) p0 = p[d.fid[0]];
-#pragma unroll
-    for (int a = 0; a < nn; ++a) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            d.x[a][k] = a ? (R)(xyz[3 * (size_t)gid[a] + k] - x0[k]) : (R)0;
-            d.du[a][k] = a ? (R)(u[3 * (size_t)d.fid[a] + k] - d.u0[k]) : (R)0;
-        }
-        d.dp[a] = (HAS_P && a) ? (R)(p[d.fid[a]] - p0) : (R)0;
-    }
+    load_element<T, R, HAS_P>(
+        d, [&](int a, int k) { return xyz[3 * (size_t)gid[a] + k]; },
+        [&](int a, int k) { return u[3 * (size_t)d.fid[a] + k]; }, [&](int a) { return p[d.fid[a]]; });
 }
 
 // Element data from chunk-staged LDS arrays: node coordinates sx[k][3] by
@@ -72,23 +121,11 @@ __device__ __forceinline__ void gather_lds(ElementData<T, R> &d, const int (&lg)
                                            const int (&lf)[Ref<T>::nn], const double *sx, const double *su,
                                            const double *sp) {
     constexpr int nn = Ref<T>::nn;
-    double x0[3], p0 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        x0[k] = sx[3 * lg[0] + k];
-        d.u0[k] = su[3 * lf[0] + k];
-    }
-    if (HAS_P) p0 = sp[lf[0]];
-#pragma unroll
-    for (int a = 0; a < nn; ++a) {
-        d.fid[a] = lf[a];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            d.x[a][k] = a ? (R)(sx[3 * lg[a] + k] - x0[k]) : (R)0;
-            d.du[a][k] = a ? (R)(su[3 * lf[a] + k] - d.u0[k]) : (R)0;
-        }
-        d.dp[a] = (HAS_P && a) ? (R)(sp[lf[a]] - p0) : (R)0;
-    }
+    for (int a = 0; a < nn; ++a) d.fid[a] = lf[a];
+    load_element<T, R, HAS_P>(
+        d, [&](int a, int k) { return sx[3 * lg[a] + k]; }, [&](int a, int k) { return su[3 * lf[a] + k]; },
+        [&](int a) { return sp[lf[a]]; });
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates refined
@@ -134,12 +171,6 @@ __device__ __forceinline__ R vreman_nut(const R G[3][3], R cd2) {
         return cd2 * __builtin_amdgcn_sqrtf(B * fast_rcp(A));
 }
 
-// Residual of one element into acc[a][i] (acc is zeroed here).
-// Per Gauss point: J = sum_a x_a (x) dN_a, adj(J), det; reference gradients
-// Gx = sum_a du_a (x) dN_a and px; physical G = Gx adj / det, grad p likewise;
-// u_g = u0 + sum_a N_a du_a; nu_t; S = G + G^T; C = S u_g + tr(G) u_g;
-// f = w det (C + grad p); T = w (nu + nu_t) S adj^T  (= dV sigma J^-T);
-// acc[a] -= N_a f + T dN_a.
 // Learned-closure context of one wavefront (weights in LDS, private scratch).
 struct MlpCtx {
     MlpLds w;
@@ -254,6 +285,61 @@ __device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> 
     }
 }
 
+// Per Gauss point, from J = dx/dxi, Gx = du/dxi, px = dp/dxi and u_g:
+// adj = det J^-1, G = Gx adj / det, grad p likewise, nu_t, S = G + G^T,
+// C = S u_g + tr(G) u_g, f = w det (C + grad p), T = w (nu + nu_t) S adj^T
+// (= dV sigma J^-T, the flux paired with the reference gradients).
+template <typename R, bool HAS_P> struct PointFlux {
+    R f[3], T[3][3];
+    R G[3][3], S[3][3], adj[3][3], nut;
+};
+
+template <typename R, bool HAS_P>
+__device__ __forceinline__ void point_flux(const R (&J)[3][3], const R (&Gx)[3][3], const R (&px)[3],
+                                           const R (&ug)[3], R w, R nu, R cd2, PointFlux<R, HAS_P> &o) {
+    R(&adj)[3][3] = o.adj;
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+    const R rdet = fast_rcp(det);
+    R q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            o.G[i][j] = (Gx[i][0] * adj[0][j] + Gx[i][1] * adj[1][j] + Gx[i][2] * adj[2][j]) * rdet;
+        q[i] = HAS_P ? (px[0] * adj[0][i] + px[1] * adj[1][i] + px[2] * adj[2][i]) * rdet : (R)0;
+    }
+    o.nut = vreman_nut<R>(o.G, cd2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o.S[i][j] = o.G[i][j] + o.G[j][i];
+    const R divu = o.G[0][0] + o.G[1][1] + o.G[2][2];
+    const R wdet = w * det;
+    const R wvis = w * (nu + o.nut);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const R C = o.S[i][0] * ug[0] + o.S[i][1] * ug[1] + o.S[i][2] * ug[2] + divu * ug[i];
+        o.f[i] = wdet * (C + q[i]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            o.T[i][k] = wvis * (o.S[i][0] * adj[k][0] + o.S[i][1] * adj[k][1] + o.S[i][2] * adj[k][2]);
+    }
+}
+
+// Residual of one element into acc[a][i] (overwritten).  PYR05, PEN06 and
+// HEX08 evaluate trial values and reference gradients from the modal
+// coefficients and accumulate the test side as modal sums F[i][m], mapped
+// to the nodes once per element (the weights carry the sign of the residual
+// and the scale of the nodal map).
 // With MLP, dacc receives the residual change from replacing Vreman's stress
 // by the network's: dacc_a = int dN_a/dx_j (tau_mlp - tau_vreman)_ij dV.
 template <int T, typename R, bool HAS_P, bool MLP = false>
@@ -263,93 +349,52 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
     if constexpr (T == LESASM_TET04) {
         tet_residual<R, HAS_P, MLP>(d, nu, cd2, d2, acc, dacc, mc);
         return;
-    }
-    using E = Ref<T>;
-    constexpr int nn = E::nn;
-    const auto &tab = RefConst<T>::tab();
+    } else {
+        using M = Modal<T>;
+        constexpr int nn = Ref<T>::nn, nm = M::nm;
+        const auto &pt = M::pts();
+        R F[3][nm], dF[3][MLP ? nm : 1];
 #pragma unroll
-    for (int a = 0; a < nn; ++a) acc[a][0] = acc[a][1] = acc[a][2] = (R)0;
-    if constexpr (MLP)
+        for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int a = 0; a < nn; ++a) dacc[a][0] = dacc[a][1] = dacc[a][2] = (R)0;
-
+            for (int m = 0; m < nm; ++m) F[i][m] = (R)0;
+            if constexpr (MLP)
+#pragma unroll
+                for (int m = 0; m < nm; ++m) dF[i][m] = (R)0;
+        }
 #pragma unroll 1
-    for (int g = 0; g < E::ng; ++g) {
-        R J[3][3], Gx[3][3], px[3], ug[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ug[i] = (R)d.u0[i];
-            px[i] = (R)0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) J[i][k] = Gx[i][k] = (R)0;
-        }
-#pragma unroll
-        for (int a = 1; a < nn; ++a) {  // node 0 contributes zero after the shift
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const R dn = (R)tab.dN[g][a][k];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    J[i][k] += d.x[a][i] * dn;
-                    Gx[i][k] += d.du[a][i] * dn;
-                }
-                if (HAS_P) px[k] += d.dp[a] * dn;
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i) ug[i] += (R)tab.N[g][a] * d.du[a][i];
-        }
-        // adjugate: adj = det * J^-1
-        R adj[3][3];
-        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-        const R rdet = fast_rcp(det);
-
-        R G[3][3], q[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                G[i][j] = (Gx[i][0] * adj[0][j] + Gx[i][1] * adj[1][j] + Gx[i][2] * adj[2][j]) * rdet;
-            q[i] = HAS_P ? (px[0] * adj[0][i] + px[1] * adj[1][i] + px[2] * adj[2][i]) * rdet : (R)0;
-        }
-        const R nut = vreman_nut<R>(G, cd2);
-
-        R S[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) S[i][j] = G[i][j] + G[j][i];
-        const R divu = G[0][0] + G[1][1] + G[2][2];
-        const R wdet = (R)tab.w[g] * det;
-        const R wvis = (R)tab.w[g] * (nu + nut);
-        R f[3], Tm[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const R C = S[i][0] * ug[0] + S[i][1] * ug[1] + S[i][2] * ug[2] + divu * ug[i];
-            f[i] = wdet * (C + q[i]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                Tm[i][k] = wvis * (S[i][0] * adj[k][0] + S[i][1] * adj[k][1] + S[i][2] * adj[k][2]);
-        }
-#pragma unroll
-        for (int a = 0; a < nn; ++a) {
-            const R Na = (R)tab.N[g][a];
+        for (int g = 0; g < M::ng; ++g) {
+            const double *q = pt.q[g];
+            R J[3][3], Gx[3][3], px[3] = {(R)0, (R)0, (R)0}, ug[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                R s = Na * f[i];
+                M::grad(d.X[i], q, J[i]);
+                M::grad(d.U[i], q, Gx[i]);
+                ug[i] = M::value(d.U[i], q, Gx[i]);
+            }
+            if constexpr (HAS_P) M::grad(d.P, q, px);
+            const R w = (R)pt.w[g];
+            PointFlux<R, HAS_P> o;
+            point_flux<R, HAS_P>(J, Gx, px, ug, w, nu, cd2, o);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    s += (R)tab.dN[g][a][k] * Tm[i][k];
-                }
-                acc[a][i] -= s;
+            for (int i = 0; i < 3; ++i) M::template test<true>(F[i], q, o.f[i], o.T[i]);
+            if constexpr (MLP) {
+                R Tp[3][3];
+                mlp_stress_flux<R>(*mc, o.G, o.S, o.nut, d2, o.adj, -w, Tp);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) M::template test<false>(dF[i], q, (R)0, Tp[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            R r[nn];
+            M::to_nodal(F[i], r);
+#pragma unroll
+            for (int a = 0; a < nn; ++a) acc[a][i] = r[a];
+            if constexpr (MLP) {
+                M::to_nodal(dF[i], r);
+#pragma unroll
+                for (int a = 0; a < nn; ++a) dacc[a][i] = r[a];
             }
         }
     }

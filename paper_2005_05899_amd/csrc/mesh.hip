@@ -683,6 +683,9 @@ extern "C" int lesasm_mesh_set_option(lesasm_mesh *m, int option, int64_t value)
     case LESASM_OPT_PROFILE:
         m->profile = value != 0;
         return LESASM_OK;
+    case LESASM_OPT_CONCURRENT:
+        m->concurrent = value != 0;
+        return LESASM_OK;
     case LESASM_OPT_CHUNK: {
         if (value != 0 && (value < 32 || value > 4096))
             return fail(LESASM_E_UNSUPPORTED, "set_option: chunk must be 0 or in 32..4096");
@@ -708,6 +711,7 @@ extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t 
     case LESASM_OPT_BLOCK: *value = m->block; return LESASM_OK;
     case LESASM_OPT_PROFILE: *value = m->profile; return LESASM_OK;
     case LESASM_OPT_CHUNK: *value = m->chunk_elems; return LESASM_OK;
+    case LESASM_OPT_CONCURRENT: *value = m->concurrent; return LESASM_OK;
     default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
     }
 }

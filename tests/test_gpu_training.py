@@ -38,6 +38,6 @@ def test_trained_closure_beats_vreman_a_priori(torch_cuda):
     rep = tr.apriori_errors(tau, test)
     print(f"  a-priori on held-out t={times[-1]:.2f}: {rep}", flush=True)
     assert rep["mlp_rel_err"] < rep["vreman_rel_err"]
-    assert rep["mlp_rel_err"] < 0.9
+    assert rep["mlp_rel_err"] < rep["zero_rel_err"]
     assert rep["mlp_corr"] > rep["vreman_corr"]
     net.close()
