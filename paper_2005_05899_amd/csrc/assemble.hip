@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const doubl
                                                         const double *__restrict__ u,
                                                         const double *__restrict__ p, double nu, double cv,
                                                         double *__restrict__ rhs) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     chunk_body<T, R, HAS_P, PERIODIC, STAGED>(c, xcd_block(blockIdx.x, gridDim.x), lds, xyz, u, p, nu, cv, rhs);
 }
 
@@ -57,21 +57,20 @@ __global__ __launch_bounds__(256) void k_assemble_chunk_mlp(ChunkView c, const d
                                                             const double *__restrict__ p, double nu, double cv,
                                                             double *__restrict__ rhs, ClosureView cl,
                                                             int lds_node_doubles) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     chunk_body<T, R, HAS_P, PERIODIC, STAGED, true>(c, xcd_block(blockIdx.x, gridDim.x), lds, xyz, u, p, nu, cv,
                                                     rhs, &cl, lds_node_doubles);
 }
 
 // Staged scatter, second phase: every node owned by no chunk sums its staging
-// rows in a fixed order (deterministic) and stores the result.
+// rows (consecutive, in a fixed order: deterministic) and stores the result.
 __global__ void k_gather_shared(const int32_t *__restrict__ gnode, const int32_t *__restrict__ goffs,
-                                const int32_t *__restrict__ gslots, const double *__restrict__ stage,
-                                double *__restrict__ rhs, int n) {
+                                const double *__restrict__ stage, double *__restrict__ rhs, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = goffs[i]; q < goffs[i + 1]; ++q) {
-        const double *row = stage + 3 * (size_t)gslots[q];
+        const double *row = stage + 3 * (size_t)q;
         s0 += row[0];
         s1 += row[1];
         s2 += row[2];
@@ -249,7 +248,7 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
     if (staged && m->n_gather > 0) {
         ProfileScope ps(m, LESASM_KERNEL_GATHER, s);
         hipLaunchKernelGGL(k_gather_shared, dim3((m->n_gather + 255) / 256), dim3(256), 0, s, m->d_gnode, m->d_goffs,
-                           m->d_gslots, m->d_stage, rhs, m->n_gather);
+                           m->d_stage, rhs, m->n_gather);
     }
     LESASM_HIP_TRY(hipGetLastError());
     return LESASM_OK;

@@ -42,7 +42,7 @@ struct BatchCall {
 
 // Per-mesh arrays for the gather and update kernels.
 struct BatchMeshDev {
-    const int32_t *gnode, *goffs, *gslots;
+    const int32_t *gnode, *goffs;
     const double *stage, *mass;
 };
 
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_batch_assemble(const BatchEntry *__rest
                                                         const BatchCall *__restrict__ call,
                                                         const int32_t *__restrict__ wentry,
                                                         const int32_t *__restrict__ wchunk, int nwork, int *head) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     __shared__ int item;
     for (;;) {
         if (threadIdx.x == 0) item = atomicAdd(head, 1);
@@ -108,7 +108,7 @@ __global__ void k_batch_gather(const BatchMeshDev *__restrict__ md, const BatchC
     const int k = (int)(i - gprefix[mi]);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = d.goffs[k]; q < d.goffs[k + 1]; ++q) {
-        const double *row = d.stage + 3 * (size_t)d.gslots[q];
+        const double *row = d.stage + 3 * (size_t)q;
         s0 += row[0];
         s1 += row[1];
         s2 += row[2];
@@ -293,7 +293,7 @@ int build_tables(lesasm_batch *b) {
     std::vector<int64_t> gp(n + 1, 0), np(n + 1, 0);
     for (int i = 0; i < n; ++i) {
         lesasm_mesh *m = b->meshes[i];
-        md[i] = BatchMeshDev{m->d_gnode, m->d_goffs, m->d_gslots, m->d_stage, m->d_mass};
+        md[i] = BatchMeshDev{m->d_gnode, m->d_goffs, m->d_stage, m->d_mass};
         gp[i + 1] = gp[i] + m->n_gather;
         np[i + 1] = np[i] + m->n_field;
     }

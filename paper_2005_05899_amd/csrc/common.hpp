@@ -135,8 +135,7 @@ struct lesasm_mesh {
     int64_t n_slots = 0;
     int32_t n_gather = 0;           // field nodes owned by no chunk
     int32_t *d_gnode = nullptr;     // [n_gather] their ids
-    int32_t *d_goffs = nullptr;     // [n_gather+1] CSR offsets into d_gslots
-    int32_t *d_gslots = nullptr;    // staging rows, in (type, chunk) order
+    int32_t *d_goffs = nullptr;     // [n_gather+1] first staging row of each shared node (rows consecutive)
     // side streams and events running the four type kernels concurrently
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     // learned closure (NULL: Vreman)

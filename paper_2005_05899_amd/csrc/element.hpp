@@ -114,18 +114,32 @@ __device__ __forceinline__ void gather(ElementData<T, R> &d, const CatView &c, i
         [&](int a, int k) { return u[3 * (size_t)d.fid[a] + k]; }, [&](int a) { return p[d.fid[a]]; });
 }
 
-// Element data from chunk-staged LDS arrays: node coordinates sx[k][3] by
-// local geometry slot, velocity su[k][3] and pressure sp[k] by local field slot.
+// Element data from chunk-staged LDS records of 32 bytes: coordinates
+// sx[k] = (x, y, z, -) by local geometry slot, velocity and pressure
+// su[k] = (u, v, w, p) by local field slot; each record is two 16-byte reads.
 template <int T, typename R, bool HAS_P>
 __device__ __forceinline__ void gather_lds(ElementData<T, R> &d, const int (&lg)[Ref<T>::nn],
-                                           const int (&lf)[Ref<T>::nn], const double *sx, const double *su,
-                                           const double *sp) {
+                                           const int (&lf)[Ref<T>::nn], const double *sx, const double *su) {
     constexpr int nn = Ref<T>::nn;
+    double xv[nn][3], uv[nn][3], pv[nn];
 #pragma unroll
-    for (int a = 0; a < nn; ++a) d.fid[a] = lf[a];
+    for (int a = 0; a < nn; ++a) {
+        d.fid[a] = lf[a];
+        const double2 *px = (const double2 *)(sx + 4 * lg[a]);
+        const double2 x01 = px[0], x2 = px[1];
+        xv[a][0] = x01.x;
+        xv[a][1] = x01.y;
+        xv[a][2] = x2.x;
+        const double2 *pu = (const double2 *)(su + 4 * lf[a]);
+        const double2 u01 = pu[0], u2p = pu[1];
+        uv[a][0] = u01.x;
+        uv[a][1] = u01.y;
+        uv[a][2] = u2p.x;
+        pv[a] = u2p.y;
+    }
     load_element<T, R, HAS_P>(
-        d, [&](int a, int k) { return sx[3 * lg[a] + k]; }, [&](int a, int k) { return su[3 * lf[a] + k]; },
-        [&](int a) { return sp[lf[a]]; });
+        d, [&](int a, int k) { return xv[a][k]; }, [&](int a, int k) { return uv[a][k]; },
+        [&](int a) { return pv[a]; });
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates refined
@@ -289,12 +303,16 @@ __device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> 
 // adj = det J^-1, G = Gx adj / det, grad p likewise, nu_t, S = G + G^T,
 // C = S u_g + tr(G) u_g, f = w det (C + grad p), T = w (nu + nu_t) S adj^T
 // (= dV sigma J^-T, the flux paired with the reference gradients).
+// UNSCALED (FP64 without the learned closure): G, S and grad p are kept
+// multiplied by det, which cancels from f, and 1/det is applied once to
+// nu_t (homogeneous of degree 1 in G) and to the viscous weight.  FP32 keeps
+// the scaled form, whose magnitudes stay in range for any element size.
 template <typename R, bool HAS_P> struct PointFlux {
     R f[3], T[3][3];
     R G[3][3], S[3][3], adj[3][3], nut;
 };
 
-template <typename R, bool HAS_P>
+template <typename R, bool HAS_P, bool UNSCALED>
 __device__ __forceinline__ void point_flux(const R (&J)[3][3], const R (&Gx)[3][3], const R (&px)[3],
                                            const R (&ug)[3], R w, R nu, R cd2, PointFlux<R, HAS_P> &o) {
     R(&adj)[3][3] = o.adj;
@@ -309,29 +327,36 @@ __device__ __forceinline__ void point_flux(const R (&J)[3][3], const R (&Gx)[3][
     adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const R det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
     const R rdet = fast_rcp(det);
+    const R sc = UNSCALED ? (R)1 : rdet;
     R q[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            o.G[i][j] = (Gx[i][0] * adj[0][j] + Gx[i][1] * adj[1][j] + Gx[i][2] * adj[2][j]) * rdet;
-        q[i] = HAS_P ? (px[0] * adj[0][i] + px[1] * adj[1][i] + px[2] * adj[2][i]) * rdet : (R)0;
+        for (int j = 0; j < 3; ++j) {
+            const R g = Gx[i][0] * adj[0][j] + Gx[i][1] * adj[1][j] + Gx[i][2] * adj[2][j];
+            o.G[i][j] = UNSCALED ? g : g * sc;
+        }
+        const R qi = HAS_P ? px[0] * adj[0][i] + px[1] * adj[1][i] + px[2] * adj[2][i] : (R)0;
+        q[i] = UNSCALED ? qi : qi * sc;
     }
-    o.nut = vreman_nut<R>(o.G, cd2);
+    o.nut = UNSCALED ? vreman_nut<R>(o.G, cd2) * rdet : vreman_nut<R>(o.G, cd2);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) o.S[i][j] = o.G[i][j] + o.G[j][i];
     const R divu = o.G[0][0] + o.G[1][1] + o.G[2][2];
-    const R wdet = w * det;
-    const R wvis = w * (nu + o.nut);
+    const R wdet = UNSCALED ? w : w * det;
+    const R wvis = UNSCALED ? w * (nu + o.nut) * rdet : w * (nu + o.nut);
+    // viscous stress times the weight, symmetric: 6 products
+    const R s00 = wvis * o.S[0][0], s11 = wvis * o.S[1][1], s22 = wvis * o.S[2][2];
+    const R s01 = wvis * o.S[0][1], s02 = wvis * o.S[0][2], s12 = wvis * o.S[1][2];
+    const R sw[3][3] = {{s00, s01, s02}, {s01, s11, s12}, {s02, s12, s22}};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const R C = o.S[i][0] * ug[0] + o.S[i][1] * ug[1] + o.S[i][2] * ug[2] + divu * ug[i];
         o.f[i] = wdet * (C + q[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            o.T[i][k] = wvis * (o.S[i][0] * adj[k][0] + o.S[i][1] * adj[k][1] + o.S[i][2] * adj[k][2]);
+        for (int k = 0; k < 3; ++k) o.T[i][k] = sw[i][0] * adj[k][0] + sw[i][1] * adj[k][1] + sw[i][2] * adj[k][2];
     }
 }
 
@@ -375,7 +400,7 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
             if constexpr (HAS_P) M::grad(d.P, q, px);
             const R w = (R)pt.w[g];
             PointFlux<R, HAS_P> o;
-            point_flux<R, HAS_P>(J, Gx, px, ug, w, nu, cd2, o);
+            point_flux<R, HAS_P, sizeof(R) == 8 && !MLP>(J, Gx, px, ug, w, nu, cd2, o);
 #pragma unroll
             for (int i = 0; i < 3; ++i) M::template test<true>(F[i], q, o.f[i], o.T[i]);
             if constexpr (MLP) {
@@ -404,9 +429,9 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 // chunk's distinct nodes are loaded once into LDS (coordinates, velocity,
 // pressure), every element reads them from there, and element residuals are
 // summed into per-node LDS accumulators.  Afterwards each node is written once:
-// a plain store when every element touching it lies in this chunk (owned), an
+// a plain store when every element touching it lies in this chunk (owned), a
 // staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
-//   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
+//   (x, y, z, -)[ng] | (u, v, w, p)[nf] | acc[nf][3].
 // Learned closure of a launch: packed weights, filter-width reference and
 // the fallback threshold (squared), plus a counter of Vreman fallbacks.
 struct ClosureView {
@@ -427,20 +452,19 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
     const int g0 = c.goff[j], ng = c.goff[j + 1] - g0;
     const int f0 = PERIODIC ? c.foff[j] : g0;
     const int nf = PERIODIC ? c.foff[j + 1] - f0 : ng;
-    double *sx = lds, *su = sx + 3 * ng, *sp = su + 3 * nf, *sacc = sp + nf;
+    double *sx = lds, *su = sx + 4 * ng, *sacc = su + 4 * nf;
 
     for (int k = threadIdx.x; k < ng; k += blockDim.x) {
         const size_t g = (size_t)c.gnodes[g0 + k];
-        sx[3 * k + 0] = xyz[3 * g + 0];
-        sx[3 * k + 1] = xyz[3 * g + 1];
-        sx[3 * k + 2] = xyz[3 * g + 2];
+        double2 *dst = (double2 *)(sx + 4 * k);
+        dst[0] = make_double2(xyz[3 * g + 0], xyz[3 * g + 1]);
+        dst[1] = make_double2(xyz[3 * g + 2], 0.0);
     }
     for (int k = threadIdx.x; k < nf; k += blockDim.x) {
         const size_t f = (size_t)((uint32_t)c.fnodes[f0 + k] & ~kOwnedBit);
-        su[3 * k + 0] = u[3 * f + 0];
-        su[3 * k + 1] = u[3 * f + 1];
-        su[3 * k + 2] = u[3 * f + 2];
-        sp[k] = HAS_P ? p[f] : 0.0;
+        double2 *dst = (double2 *)(su + 4 * k);
+        dst[0] = make_double2(u[3 * f + 0], u[3 * f + 1]);
+        dst[1] = make_double2(u[3 * f + 2], HAS_P ? p[f] : 0.0);
         sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
     }
     if constexpr (MLP) mlp_stage(cl->packed, cl->bias, (unsigned char *)(lds + lds_node_doubles));
@@ -455,7 +479,7 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
                 lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
             }
             ElementData<T, R> d;
-            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su);
             const double dl = c.delta[e];
             R acc[nn][3];
             element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
@@ -487,7 +511,7 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
                 lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
             }
             ElementData<T, R> d;
-            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su);
             const double dl = c.delta[e];
             mc.logd = (float)(log(dl) - cl->log_delta_ref);
             R acc[nn][3], dacc[nn][3];

@@ -272,7 +272,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
             fcount[f] = 0;
             fslot[f] = -1;
         }
-        c.lds_doubles = std::max(c.lds_doubles, (int)(3 * gl.size() + 7 * fl.size()));
+        c.lds_doubles = std::max(c.lds_doubles, (int)(4 * gl.size() + 7 * fl.size()));
         eoff.push_back((int32_t)e);
         goff.push_back((int32_t)gnodes.size());
         foff.push_back((int32_t)fnodes.size());
@@ -303,53 +303,49 @@ static int build_staging(lesasm_mesh *m) {
     dfree(m, m->d_stage);
     dfree(m, m->d_gnode);
     dfree(m, m->d_goffs);
-    dfree(m, m->d_gslots);
     m->n_slots = 0;
     m->n_gather = 0;
+    // Rows of one shared node are consecutive (node order, then type and chunk
+    // order), so the gather reads them without an index array.
     std::vector<int32_t> owned(m->n_field, 0), count(m->n_field, 0);
-    std::vector<std::vector<int32_t>> fslot(kNumCat);
-    int64_t next = 0;
+    int64_t total = 0;
     for (int k = 0; k < kNumCat; ++k) {
-        Category &c = m->cat[k];
-        dfree(m, c.d_fslot);
-        fslot[k].resize(c.h_fnodes.size());
+        const Category &c = m->cat[k];
         for (size_t q = 0; q < c.h_fnodes.size(); ++q) {
             const uint32_t tag = (uint32_t)c.h_fnodes[q];
             const int32_t f = (int32_t)(tag & ~kOwnedBit);
-            if (tag & kOwnedBit) {
-                owned[f] = 1;
-                fslot[k][q] = -1;
-            } else {
-                fslot[k][q] = (int32_t)next++;
+            if (tag & kOwnedBit) owned[f] = 1;
+            else {
                 count[f]++;
+                total++;
             }
         }
     }
-    if (next >= INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "mesh_create: too many staging rows");
+    if (total >= INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "mesh_create: too many staging rows");
     std::vector<int32_t> gnode, goffs{0};
     std::vector<int32_t> pos(m->n_field, -1);
     for (int64_t f = 0; f < m->n_field; ++f)
-        if (!owned[f]) {
-            pos[f] = (int32_t)goffs.back();
+        if (!owned[f]) {  // includes nodes of no element (count 0): the gather writes their zero
+            pos[f] = goffs.back();
             gnode.push_back((int32_t)f);
             goffs.push_back(goffs.back() + count[f]);
         }
-    std::vector<int32_t> gslots(next);
+    std::vector<std::vector<int32_t>> fslot(kNumCat);
     for (int k = 0; k < kNumCat; ++k) {
-        const Category &c = m->cat[k];
-        for (size_t q = 0; q < c.h_fnodes.size(); ++q)
-            if (fslot[k][q] >= 0) {
-                const int32_t f = (int32_t)((uint32_t)c.h_fnodes[q] & ~kOwnedBit);
-                gslots[pos[f]++] = fslot[k][q];
-            }
+        Category &c = m->cat[k];
+        dfree(m, c.d_fslot);
+        fslot[k].assign(c.h_fnodes.size(), -1);
+        for (size_t q = 0; q < c.h_fnodes.size(); ++q) {
+            const uint32_t tag = (uint32_t)c.h_fnodes[q];
+            if (!(tag & kOwnedBit)) fslot[k][q] = pos[(int32_t)(tag & ~kOwnedBit)]++;
+        }
     }
-    m->n_slots = next;
+    m->n_slots = total;
     m->n_gather = (int32_t)gnode.size();
     int st;
-    if ((st = dalloc(m, &m->d_stage, 3 * (size_t)next))) return st;
+    if ((st = dalloc(m, &m->d_stage, 3 * (size_t)total))) return st;
     if ((st = upload(m, &m->d_gnode, gnode))) return st;
     if ((st = upload(m, &m->d_goffs, goffs))) return st;
-    if ((st = upload(m, &m->d_gslots, gslots))) return st;
     for (int k = 0; k < kNumCat; ++k)
         if ((st = upload(m, &m->cat[k].d_fslot, fslot[k]))) return st;
     return LESASM_OK;
