@@ -10,7 +10,7 @@ Beside the FP64 value the line carries the mixed-precision form (FP32 element
 contractions) and, if trained weights are present, the learned closure, each
 with its error against the FP64 CPU oracle on the same inputs.  The batched
 workload (64 partitions, about 25 M elements, persistent launch) is a separate
-mode: --workload batch64; the 20 M-element precision comparison (FP32
+mode: --workload batch64; the all-tetrahedron box (20.25 M TET04) is --workload tet20m; the 20 M-element precision comparison (FP32
 contractions and a full time step in both precisions) is --workload precision20m.
 """
 from __future__ import annotations
@@ -106,6 +106,14 @@ def time_assembly(torch, mesh, u, p, nu, steps, warmup, concurrent=True):
     return elapsed, kt, rhs
 
 
+def fallback_fraction(mesh, u, p, nu) -> float:
+    """Fraction of elements that kept Vreman's stress in one assembly."""
+    from paper_2005_05899_amd import lesasm
+    lesasm.closure_fallbacks(mesh)  # resets the counter
+    mesh.assemble_momentum_rhs(u, p, nu)
+    return lesasm.closure_fallbacks(mesh) / mesh.n_elems
+
+
 def cpu_baseline(case, min_seconds: float = 10.0) -> dict:
     """The FP64 oracle, single thread, repeated on the whole workload until
     at least min_seconds of CPU time; median rate."""
@@ -123,10 +131,10 @@ def cpu_baseline(case, min_seconds: float = 10.0) -> dict:
                       f"({total:.1f} s), median rate"}
 
 
-def traffic_from_profiles(slot: str):
+def traffic_from_profiles(slot: str, workload: str = "hybrid2m"):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_k_assemble_{slot}_hybrid2m.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_k_assemble_{slot}_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -139,7 +147,7 @@ def run_main(args):
     import torch
     from paper_2005_05899_amd import lesasm, meshgen
     torch.cuda.set_device(0)
-    case = meshgen.hybrid_2m_case()
+    case = meshgen.tet_case(150) if args.workload == "tet20m" else meshgen.hybrid_2m_case()
     m = case.mesh
     mesh = lesasm.Mesh.from_arrays(m, case.vreman_c, scatter=args.scatter)
     mesh.precision = args.precision
@@ -183,7 +191,7 @@ def run_main(args):
     ab = algorithmic_bytes(m, True)
     step_s = elapsed / args.steps
     total_flops = sum(FLOPS_PER_ELEMENT[t] * mesh.n_per_type[t] for t in SLOT)
-    traffic = traffic_from_profiles(dominant)
+    traffic = traffic_from_profiles(dominant, args.workload)
     out = {
         "metric": "element-assemblies/s + % HBM peak; mixed/learned vs FP64 at stated error",
         "value": value,
@@ -197,8 +205,10 @@ def run_main(args):
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic (seeded hybrid mesh and random Fourier fields; the paper's airplane meshes are not used)",
-        "config": {"workload": "hybrid box, 2.0M elements (TET04/PEN06/PYR05/HEX08 = 40/40/5/15 %), "
-                               f"{args.precision}, {args.scatter} scatter",
+        "config": {"workload": ("all-TET04 box, 20.25M elements (150^3 cells x 6), "
+                                if args.workload == "tet20m" else
+                                "hybrid box, 2.0M elements (TET04/PEN06/PYR05/HEX08 = 40/40/5/15 %), ")
+                               + f"{args.precision}, {args.scatter} scatter",
                    "elements": E, "field_nodes": m.n_field_nodes,
                    "per_type": {SLOT[t]: mesh.n_per_type[t] for t in SLOT},
                    "nu": case.nu, "vreman_c": case.vreman_c, "seeds": case.meta},
@@ -233,13 +243,11 @@ def run_main(args):
             for prec in ("fp32", "fp64"):
                 mesh.precision = prec
                 lesasm.set_closure(mesh, net, meta.get("delta_ref", 0.1), 0.05)
-                lesasm.closure_fallbacks(mesh)
                 el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
-                fb = lesasm.closure_fallbacks(mesh)
                 variants[f"learned_closure_{prec}"] = {
                     "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
                     "speedup_vs_fp64_vreman": elapsed / el,
-                    "fallback_fraction": fb / (E * (args.steps + args.warmup)),
+                    "fallback_fraction": fallback_fraction(mesh, u, p, case.nu),
                     "difference_vs_fp64_vreman_oracle": field_errors(mesh.to_user(rl).cpu().numpy(), ref)}
                 lesasm.set_closure(mesh, None)
             net.close()
@@ -391,12 +399,10 @@ def run_precision(args):
         for prec in ("fp32", "fp64"):
             mesh.precision = prec
             lesasm.set_closure(mesh, net, meta.get("delta_ref", 0.1), 0.05)
-            lesasm.closure_fallbacks(mesh)
             el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
-            fb = lesasm.closure_fallbacks(mesh)
             variants[f"learned_closure_{prec}"] = {
                 "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-                "fallback_fraction": fb / (E * (args.steps + args.warmup)),
+                "fallback_fraction": fallback_fraction(mesh, u, p, case.nu),
                 "difference_vs_fp64_vreman_oracle": field_errors(mesh.to_user(rl).cpu().numpy(), ref)}
             lesasm.set_closure(mesh, None)
         net.close()
@@ -449,7 +455,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["hybrid2m", "batch64", "precision20m", "copy"], default="hybrid2m")
+    ap.add_argument("--workload", choices=["hybrid2m", "tet20m", "batch64", "precision20m", "copy"], default="hybrid2m")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--scatter", choices=["staged", "chunk_atomic", "colour", "direct"], default="staged")
     ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatters)")

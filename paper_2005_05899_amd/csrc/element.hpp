@@ -430,8 +430,9 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 // pressure), every element reads them from there, and element residuals are
 // summed into per-node LDS accumulators.  Afterwards each node is written once:
 // a plain store when every element touching it lies in this chunk (owned), a
-// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
-//   (x, y, z, -)[ng] | (u, v, w, p)[nf] | acc[nf][3].
+// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout:
+//   (x, y, z, -)[ng] | (u, v, w, p)[nf] | acc[nf][3] doubles, then 16-byte
+//   element records: geometry slots [ne], field slots [ne] (periodic), widths.
 // Learned closure of a launch: packed weights, filter-width reference and
 // the fallback threshold (squared), plus a counter of Vreman fallbacks.
 struct ClosureView {
@@ -441,6 +442,13 @@ struct ClosureView {
     double tol2;
     unsigned long long *fallbacks;
 };
+
+// The first n 16-bit slots of a 16-byte element record.
+template <int N> __device__ __forceinline__ void unpack_slots(const uint4 r, int (&s)[N]) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int a = 0; a < N; ++a) s[a] = (int)((w[a >> 1] >> (16 * (a & 1))) & 0xffffu);
+}
 
 template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED, bool MLP = false>
 __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *lds, const double *__restrict__ xyz,
@@ -453,6 +461,12 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
     const int f0 = PERIODIC ? c.foff[j] : g0;
     const int nf = PERIODIC ? c.foff[j + 1] - f0 : ng;
     double *sx = lds, *su = sx + 4 * ng, *sacc = su + 4 * nf;
+    // element records after the node records (16-byte aligned): local geometry
+    // slots, local field slots (periodic meshes), filter widths
+    const int ne = e1 - e0;
+    uint4 *sig = (uint4 *)(lds + ((4 * ng + 7 * nf + 1) & ~1));
+    uint4 *sif = PERIODIC ? sig + ne : sig;
+    double *sdl = (double *)(sig + (PERIODIC ? 2 * ne : ne));
 
     for (int k = threadIdx.x; k < ng; k += blockDim.x) {
         const size_t g = (size_t)c.gnodes[g0 + k];
@@ -467,20 +481,25 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
         dst[1] = make_double2(u[3 * f + 2], HAS_P ? p[f] : 0.0);
         sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
     }
+    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+        sig[k] = ((const uint4 *)c.lg)[e0 + k];
+        if (PERIODIC) sif[k] = ((const uint4 *)c.lf)[e0 + k];
+        sdl[k] = c.delta[e0 + k];
+    }
     if constexpr (MLP) mlp_stage(cl->packed, cl->bias, (unsigned char *)(lds + lds_node_doubles));
     __syncthreads();
 
     if constexpr (!MLP) {
         for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
             int lg[nn], lf[nn];
+            unpack_slots<nn>(sig[e - e0], lg);
+            if (PERIODIC) unpack_slots<nn>(sif[e - e0], lf);
+            else
 #pragma unroll
-            for (int a = 0; a < nn; ++a) {
-                lg[a] = c.lg[(size_t)a * c.ld + e];
-                lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
-            }
+                for (int a = 0; a < nn; ++a) lf[a] = lg[a];
+            const double dl = sdl[e - e0];
             ElementData<T, R> d;
             gather_lds<T, R, HAS_P>(d, lg, lf, sx, su);
-            const double dl = c.delta[e];
             R acc[nn][3];
             element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
 #pragma unroll
@@ -505,14 +524,14 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
             const bool active = base + (int)threadIdx.x < e1;
             const int e = active ? base + (int)threadIdx.x : e1 - 1;
             int lg[nn], lf[nn];
+            unpack_slots<nn>(sig[e - e0], lg);
+            if (PERIODIC) unpack_slots<nn>(sif[e - e0], lf);
+            else
 #pragma unroll
-            for (int a = 0; a < nn; ++a) {
-                lg[a] = c.lg[(size_t)a * c.ld + e];
-                lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
-            }
+                for (int a = 0; a < nn; ++a) lf[a] = lg[a];
             ElementData<T, R> d;
             gather_lds<T, R, HAS_P>(d, lg, lf, sx, su);
-            const double dl = c.delta[e];
+            const double dl = sdl[e - e0];
             mc.logd = (float)(log(dl) - cl->log_delta_ref);
             R acc[nn][3], dacc[nn][3];
             element_residual<T, R, HAS_P, true>(d, (R)nu, (R)(cv * dl * dl), acc, (R)(dl * dl), dacc, &mc);

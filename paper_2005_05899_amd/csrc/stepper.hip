@@ -234,6 +234,96 @@ __global__ void k_reduce_final(const double *__restrict__ partial, int nb, doubl
     if (threadIdx.x == 0) *out = sh[0];
 }
 
+// Conjugate-gradient kernels.  A fixed grid (kCgBlocks x 256) walks the rows
+// in a fixed order, so every reduction is deterministic.
+constexpr int kCgBlocks = 1024;
+constexpr int kLanesPerRow = 8;
+
+// Fixed-order sum of one value per thread of a 256-thread block into out[0].
+__device__ __forceinline__ void block_sum_256(double v, double *sh, double *out) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+    __syncthreads();
+}
+
+// q = K p with 8 lanes per row (coalesced reads of the row's entries, fixed
+// shuffle tree), and partial[b] = block sums of p.q.
+__global__ __launch_bounds__(256) void k_spmv_dot(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                  const double *__restrict__ val, const double *__restrict__ p,
+                                                  double *__restrict__ q, int n, double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int lane = threadIdx.x % kLanesPerRow;
+    const int rows_per_block = 256 / kLanesPerRow;
+    double pq = 0.0;
+    for (int base = blockIdx.x * rows_per_block; base < n; base += gridDim.x * rows_per_block) {
+        const int row = base + (int)threadIdx.x / kLanesPerRow;
+        double s = 0.0;
+        if (row < n)
+            for (int k = rowptr[row] + lane; k < rowptr[row + 1]; k += kLanesPerRow) s += val[k] * p[col[k]];
+#pragma unroll
+        for (int o = kLanesPerRow / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kLanesPerRow);
+        if (lane == 0 && row < n) {
+            q[row] = s;
+            pq += s * p[row];
+        }
+    }
+    block_sum_256(pq, sh, partial + blockIdx.x);
+}
+
+// alpha = rz / pq;  x += alpha p;  r -= alpha q;  z = r / diag;
+// partial[2b] = block sums of r.z, partial[2b+1] = of r.r
+__global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ z, const double *__restrict__ p,
+                                                   const double *__restrict__ q, const double *__restrict__ diag,
+                                                   const double *__restrict__ scal, int i_rz, int i_pq, int n,
+                                                   double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const double alpha = scal[i_rz] / scal[i_pq];
+    double rz = 0.0, rr = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        const double zi = ri / diag[i];
+        r[i] = ri;
+        z[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+    block_sum_256(rz, sh, partial + 2 * blockIdx.x);
+    block_sum_256(rr, sh, partial + 2 * blockIdx.x + 1);
+}
+
+// out[j] = fixed-order sum of partial[stride * b + j] over b < nb, for j < m
+// (one 1024-thread block).
+__global__ __launch_bounds__(1024) void k_reduce_strided(const double *__restrict__ partial, int nb, int stride,
+                                                         int m, double *__restrict__ out0, double *__restrict__ out1) {
+    __shared__ double sh[1024];
+    for (int j = 0; j < m; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) v += partial[stride * b + j];
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *(j == 0 ? out0 : out1) = sh[0];
+        __syncthreads();
+    }
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ __launch_bounds__(256) void k_cg_direction(double *__restrict__ p, const double *__restrict__ z,
+                                                      const double *__restrict__ scal, int i_new, int i_old, int n) {
+    const double beta = scal[i_new] / scal[i_old];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+}
+
 // y = a0 x0 + a1 x1 + a2 x2 (x1, x2 may be NULL)
 __global__ void k_lincomb(double *__restrict__ y, double a0, const double *__restrict__ x0, double a1,
                           const double *__restrict__ x1, double a2, const double *__restrict__ x2, size_t n) {
@@ -318,7 +408,7 @@ using namespace lesasm;
 struct lesasm_stepper {
     lesasm_mesh *mesh = nullptr;
     double nu = 0.0, dt = 0.0, rtol = 1e-12;
-    int maxit = 1000, check_every = 8;
+    int maxit = 1000, check_every = 16;
     int n = 0;
     int32_t *rowptr = nullptr, *col = nullptr;
     double *val = nullptr, *diag = nullptr;
@@ -382,21 +472,22 @@ int pressure_solve(lesasm_stepper *st, const double *b_in, double *x, hipStream_
     int it = 0;
     double res = bnorm;
     if (bnorm > 0.0) {
+        // rz lives in two slots used alternately, so no scalar is overwritten
+        // while a kernel may still read it.
+        int i_rz = S_RZ, i_rzn = S_RZN;
         for (it = 1; it <= st->maxit; ++it) {
-            hipLaunchKernelGGL(k_spmv, dim3((n + 255) / 256), dim3(256), 0, s, st->rowptr, st->col, st->val, st->pv,
-                               st->q, n);
-            dot(st, st->pv, st->q, S_PQ, s);
-            hipLaunchKernelGGL(k_axpy_ratio, dim3(g), dim3(256), 0, s, x, st->pv, st->scal + S_RZ, st->scal + S_PQ,
-                               1.0, n);
-            hipLaunchKernelGGL(k_axpy_ratio, dim3(g), dim3(256), 0, s, st->r, st->q, st->scal + S_RZ,
-                               st->scal + S_PQ, -1.0, n);
-            hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(256), 0, s, st->z, st->r, st->diag, n);
-            dot(st, st->r, st->z, S_RZN, s);
-            hipLaunchKernelGGL(k_xpby_ratio, dim3(g), dim3(256), 0, s, st->pv, st->z, st->scal + S_RZN,
-                               st->scal + S_RZ, n);
-            LESASM_HIP_TRY(hipMemcpyAsync(st->scal + S_RZ, st->scal + S_RZN, sizeof(double), hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_spmv_dot, dim3(kCgBlocks), dim3(256), 0, s, st->rowptr, st->col, st->val, st->pv,
+                               st->q, n, st->partial);
+            hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 1, 1,
+                               st->scal + S_PQ, st->scal + S_PQ);
+            hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(256), 0, s, x, st->r, st->z, st->pv, st->q,
+                               st->diag, st->scal, i_rz, S_PQ, n, st->partial);
+            hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 2, 2,
+                               st->scal + i_rzn, st->scal + S_RR);
+            hipLaunchKernelGGL(k_cg_direction, dim3(kCgBlocks), dim3(256), 0, s, st->pv, st->z, st->scal, i_rzn,
+                               i_rz, n);
+            std::swap(i_rz, i_rzn);
             if (it % st->check_every == 0 || it == st->maxit) {
-                dot(st, st->r, st->r, S_RR, s);
                 LESASM_HIP_TRY(hipMemcpyAsync(host, st->scal, sizeof(host), hipMemcpyDeviceToHost, s));
                 LESASM_HIP_TRY(hipStreamSynchronize(s));
                 res = std::sqrt(host[S_RR]);
@@ -503,7 +594,7 @@ extern "C" int lesasm_stepper_create(lesasm_mesh *m, double nu, double dt, doubl
         (rc = salloc(st, &st->gdp, 3 * (size_t)n)) || (rc = salloc(st, &st->b, (size_t)n)) ||
         (rc = salloc(st, &st->x, (size_t)n)) || (rc = salloc(st, &st->r, (size_t)n)) ||
         (rc = salloc(st, &st->z, (size_t)n)) || (rc = salloc(st, &st->pv, (size_t)n)) ||
-        (rc = salloc(st, &st->q, (size_t)n)) || (rc = salloc(st, &st->partial, kRedBlocks)) ||
+        (rc = salloc(st, &st->q, (size_t)n)) || (rc = salloc(st, &st->partial, 2 * kCgBlocks)) ||
         (rc = salloc(st, &st->scal, S_NUM)))
         return rc;
     if (n) {

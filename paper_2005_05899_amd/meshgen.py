@@ -454,6 +454,20 @@ def hybrid_20m_case() -> Case:
     return hybrid_case(20_000_000, seed_mesh=4, seed_u=5, seed_p=12, n_xy=205)
 
 
+def tet_case(n_xy: int = 150, nz: int | None = None, seed_mesh: int = 8, seed_u: int = 9, seed_p: int = 13,
+             nu: float = 1.5e-5, c: float = 0.1) -> Case:
+    """All-TET04 box: the graded, perturbed hex grid of hybrid_box with every
+    cell split into 6 tetrahedra (n_xy = 150: 150 x 150 x 150 cells, 20.25 M
+    elements), random Fourier velocity and smooth pressure as hybrid_case."""
+    nz = n_xy if nz is None else nz
+    mesh = hybrid_box(n_xy, n_xy, [(TET04, nz)], seed=seed_mesh)
+    xf = mesh.field_coords()
+    u = random_fourier_velocity(seed=seed_u)(xf)
+    p = random_fourier_scalar(seed=seed_p)(xf)[:, 0]
+    return Case(f"tet_{mesh.n_elems}", mesh, u, p, nu, c,
+                meta={"seed_mesh": seed_mesh, "seed_u": seed_u, "seed_p": seed_p, "n_xy": n_xy, "nz": nz})
+
+
 def small_hybrid_case(nx: int = 5, ny: int = 4, layers=None, seed: int = 7, nu: float = 0.05,
                       c: float = 0.1, with_p: bool = True) -> Case:
     """A few hundred elements of every type (several tiles plus ragged tails)."""
