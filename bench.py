@@ -106,6 +106,31 @@ def time_assembly(torch, mesh, u, p, nu, steps, warmup, concurrent=True):
     return elapsed, kt, rhs
 
 
+def time_wall(torch, mesh, m, case, u, steps) -> dict:
+    """The boundary assembly of the wall model (wall z = 0): time per call and
+    error against the oracle."""
+    import oracle
+    from paper_2005_05899_amd import meshgen
+    faces = meshgen.wall_faces(m)
+    mesh.set_wall(*faces)
+    out = torch.zeros_like(u)
+    for _ in range(3):
+        mesh.assemble_wall(u, case.nu, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mesh.assemble_wall(u, case.nu, out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out.zero_()
+    mesh.assemble_wall(u, case.nu, out)
+    ref, *_ = oracle.wall_assemble(m, case.u, case.nu, *faces)
+    got = mesh.to_user(out).cpu().numpy()
+    mesh.set_wall(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64))
+    return {"faces": int(len(faces[2])), "ms_per_call": 1e3 * el / steps,
+            "error_vs_oracle": field_errors(got, ref)}
+
+
 def fallback_fraction(mesh, u, p, nu) -> float:
     """Fraction of elements that kept Vreman's stress in one assembly."""
     from paper_2005_05899_amd import lesasm
@@ -252,6 +277,7 @@ def run_main(args):
                 lesasm.set_closure(mesh, None)
             net.close()
         out["variants"] = variants
+        out["wall_model"] = time_wall(torch, mesh, m, case, u, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

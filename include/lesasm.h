@@ -350,6 +350,42 @@ int lesasm_mesh_set_closure(lesasm_mesh *mesh, const lesasm_mlp *mlp, double del
  * synchronises). */
 int lesasm_mesh_closure_fallbacks(lesasm_mesh *mesh, uint64_t *count);
 
+/* ---- wall model (boundary assembly) ------------------------------------ */
+/* Algorithm 1, "Boundary assembly"; Section 3.2 names a law-of-the-wall
+ * model without its formulas.  An equilibrium wall model: for each wall face,
+ * the velocity at the vertex average of the face's volume element (the mean
+ * of its nodal velocities) and that point's distance y to the face plane give,
+ * through Reichardt's law U/u_tau = f(y u_tau/nu) (kappa 0.41, C1 7.8,
+ * chi 11), the friction velocity; the traction -u_tau^2 u_t/|u_t| (u_t the
+ * tangential part of the velocity) is added to the face nodes, weighted by the
+ * face integrals of their shape functions. */
+typedef struct lesasm_wall_desc {
+    int64_t n_faces;              /* 0 removes the wall */
+    const int64_t *face_offsets;  /* host [n_faces+1], face_offsets[0] = 0; 3 or 4 nodes per face */
+    const int32_t *face_conn;     /* host, user geometry node ids of each face, as a cycle */
+    const int64_t *face_elem;     /* host [n_faces], user id of the volume element the face bounds */
+} lesasm_wall_desc;
+
+/* Copies the wall faces (replacing any previous set); host arrays are not
+ * retained.  Synchronises.
+ * Errors: LESASM_E_INVALID_ARG (NULL, a face of neither 3 nor 4 nodes, node or
+ * element out of range), LESASM_E_STATE (wrong device), LESASM_E_OOM,
+ * LESASM_E_HIP. */
+int lesasm_mesh_set_wall(lesasm_mesh *mesh, const lesasm_wall_desc *desc);
+
+/* d_rhs[n_field][3] += wall-model contributions for velocity d_u[n_field][3]
+ * (internal order, device, 8-byte aligned, rhs not aliasing u), kinematic
+ * viscosity nu > 0.  Asynchronous on `stream`; a no-op without wall faces.
+ * Faces that share a node add with FP64 atomics (summation order varies).
+ * Errors: LESASM_E_INVALID_ARG, LESASM_E_STATE, LESASM_E_HIP. */
+int lesasm_assemble_wall(lesasm_mesh *mesh, const double *d_u, double nu, double *d_rhs, void *stream);
+
+/* Waits for all work queued on `stream` (a hipStream_t; NULL = the null
+ * stream) and reports what the asynchronous calls could not: a failed kernel
+ * or copy surfaces here as LESASM_E_HIP with the runtime's text.
+ * Errors: LESASM_E_HIP. */
+int lesasm_check(void *stream);
+
 /* Text of the calling thread's last error ("" if none). */
 const char *lesasm_last_error(void);
 

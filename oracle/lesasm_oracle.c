@@ -593,3 +593,176 @@ int oracle_element_stress_residual(int type, const double *x, const double *tau,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Boundary assembly: equilibrium wall model (Algorithm 1, "Boundary        */
+/* assembly"; Section 3.2 names a law-of-the-wall model without formulas)   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Reading (listed in the design notes):
+ *   exchange point  x_e = vertex average of the wall face's volume element,
+ *                   u_e = mean of its nodal velocities (the finite-element
+ *                   interpolant at x_e for every linear type);
+ *   wall distance   y = |n . (x_e - x_f)|, x_f the face's vertex average and
+ *                   n its unit normal (triangle: (x1-x0) x (x2-x0); quad:
+ *                   (x2-x0) x (x3-x1));
+ *   tangential velocity u_t = u_e - (u_e . n) n, U = |u_t|;
+ *   law of the wall (Reichardt): U / u_tau = f(y u_tau / nu),
+ *     f(y+) = ln(1 + kappa y+)/kappa + C1 (1 - exp(-y+/chi) - (y+/chi) exp(-y+/3)),
+ *     kappa = 0.41, C1 = 7.8, chi = 11, solved for u_tau by Newton's method;
+ *   wall shear stress tau_w = u_tau^2 (rho = 1) against the flow:
+ *     t = -tau_w u_t / U (t = 0 when U = 0);
+ *   nodal contribution rhs[a] += t * int_face N_a dA (linear triangle, or
+ *     bilinear quadrilateral with the 2 x 2 Gauss rule).
+ */
+#define WALL_KAPPA 0.41
+#define WALL_C1 7.8
+#define WALL_CHI 11.0
+
+double oracle_wall_law(double yp)
+{
+    return log(1.0 + WALL_KAPPA * yp) / WALL_KAPPA +
+           WALL_C1 * (1.0 - exp(-yp / WALL_CHI) - (yp / WALL_CHI) * exp(-yp / 3.0));
+}
+
+static double wall_law_slope(double yp)
+{
+    return 1.0 / (1.0 + WALL_KAPPA * yp) +
+           WALL_C1 * (exp(-yp / WALL_CHI) / WALL_CHI - exp(-yp / 3.0) / WALL_CHI + (yp / WALL_CHI) * exp(-yp / 3.0) / 3.0);
+}
+
+/* u_tau with U = u_tau f(y u_tau / nu); 0 when U = 0.  Newton's method on
+ * g(u) = u f(y u / nu) - U from the viscous-sublayer value sqrt(nu U / y). */
+double oracle_friction_velocity(double U, double y, double nu)
+{
+    if (!(U > 0.0)) return 0.0;
+    double ut = sqrt(nu * U / y);
+    for (int it = 0; it < 100; ++it) {
+        const double yp = y * ut / nu;
+        const double g = ut * oracle_wall_law(yp) - U;
+        const double dg = oracle_wall_law(yp) + yp * wall_law_slope(yp);
+        const double step = g / dg;
+        ut -= step;
+        if (fabs(step) <= 1e-15 * ut) break;
+    }
+    return ut;
+}
+
+/* Face integrals of the face's own shape functions, int N_a dA, for a
+ * triangle (n = 3) or a bilinear quadrilateral (n = 4), and the unit normal. */
+static int face_geometry(int n, const double *xf, double *wa, double *nrm)
+{
+    double c[3];
+    if (n == 3) {
+        double d1[3], d2[3];
+        for (int k = 0; k < 3; ++k) {
+            d1[k] = xf[3 + k] - xf[k];
+            d2[k] = xf[6 + k] - xf[k];
+        }
+        c[0] = d1[1] * d2[2] - d1[2] * d2[1];
+        c[1] = d1[2] * d2[0] - d1[0] * d2[2];
+        c[2] = d1[0] * d2[1] - d1[1] * d2[0];
+        const double area = 0.5 * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int a = 0; a < 3; ++a) wa[a] = area / 3.0;
+    } else if (n == 4) {
+        double d1[3], d2[3];
+        for (int k = 0; k < 3; ++k) {
+            d1[k] = xf[6 + k] - xf[k];
+            d2[k] = xf[9 + k] - xf[3 + k];
+        }
+        c[0] = d1[1] * d2[2] - d1[2] * d2[1];
+        c[1] = d1[2] * d2[0] - d1[0] * d2[2];
+        c[2] = d1[0] * d2[1] - d1[1] * d2[0];
+        /* nodes counter-clockwise: (-1,-1), (1,-1), (1,1), (-1,1) */
+        const double s[4] = {-1, 1, 1, -1}, t[4] = {-1, -1, 1, 1};
+        const double gq = 1.0 / sqrt(3.0);
+        for (int a = 0; a < 4; ++a) wa[a] = 0.0;
+        for (int gi = 0; gi < 2; ++gi)
+            for (int gj = 0; gj < 2; ++gj) {
+                const double xi = gi ? gq : -gq, eta = gj ? gq : -gq;
+                double dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0};
+                for (int a = 0; a < 4; ++a)
+                    for (int k = 0; k < 3; ++k) {
+                        dx[k] += 0.25 * s[a] * (1.0 + t[a] * eta) * xf[3 * a + k];
+                        dy[k] += 0.25 * t[a] * (1.0 + s[a] * xi) * xf[3 * a + k];
+                    }
+                const double cx = dx[1] * dy[2] - dx[2] * dy[1];
+                const double cy = dx[2] * dy[0] - dx[0] * dy[2];
+                const double cz = dx[0] * dy[1] - dx[1] * dy[0];
+                const double jac = sqrt(cx * cx + cy * cy + cz * cz);
+                for (int a = 0; a < 4; ++a) wa[a] += 0.25 * (1.0 + s[a] * xi) * (1.0 + t[a] * eta) * jac;
+            }
+    } else {
+        return -1;
+    }
+    const double len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    if (!(len > 0.0)) return -2;
+    for (int k = 0; k < 3; ++k) nrm[k] = c[k] / len;
+    return 0;
+}
+
+/* Wall-model contribution of every wall face into out[n_field][3]
+ * (overwritten).  Face f has the user nodes face_conn[face_offs[f] ..
+ * face_offs[f+1]) (3 or 4) and lies on volume element face_elem[f].  Optional
+ * per-face diagnostics: y, U, u_tau (each [n_faces], may be NULL). */
+int oracle_wall_assemble(int64_t n_nodes, const double *coords, int64_t n_elems, const uint8_t *types,
+                         const int64_t *offs, const int32_t *conn, const int32_t *field_node, int64_t n_field,
+                         const double *u, double nu, int64_t n_faces, const int64_t *face_offs,
+                         const int32_t *face_conn, const int64_t *face_elem, double *out, double *diag_y,
+                         double *diag_U, double *diag_ut)
+{
+    double x[3 * ORACLE_MAX_NODE], ue[3 * ORACLE_MAX_NODE];
+    int64_t fid[ORACLE_MAX_NODE];
+    g_bad_element = -1;
+    for (int64_t k = 0; k < 3 * n_field; ++k) out[k] = 0.0;
+    for (int64_t f = 0; f < n_faces; ++f) {
+        const int64_t e = face_elem[f];
+        const int nf = (int)(face_offs[f + 1] - face_offs[f]);
+        if (e < 0 || e >= n_elems || (nf != 3 && nf != 4)) { g_bad_element = f; return -1; }
+        const int n = gather(e, n_nodes, coords, types, offs, conn, field_node, n_field, u, NULL, x, ue, NULL, fid);
+        if (n < 0) { g_bad_element = f; return -1; }
+        double xe[3] = {0, 0, 0}, uel[3] = {0, 0, 0};
+        for (int a = 0; a < n; ++a)
+            for (int k = 0; k < 3; ++k) {
+                xe[k] += x[3 * a + k] / n;
+                uel[k] += ue[3 * a + k] / n;
+            }
+        double xf[12], xc[3] = {0, 0, 0};
+        int64_t ff[4];
+        for (int b = 0; b < nf; ++b) {
+            const int64_t g = face_conn[face_offs[f] + b];
+            if (g < 0 || g >= n_nodes) { g_bad_element = f; return -1; }
+            ff[b] = field_node ? (int64_t)field_node[g] : g;
+            for (int k = 0; k < 3; ++k) {
+                xf[3 * b + k] = coords[3 * g + k];
+                xc[k] += coords[3 * g + k] / nf;
+            }
+        }
+        double wa[4], nrm[3];
+        const int st = face_geometry(nf, xf, wa, nrm);
+        if (st) { g_bad_element = f; return st; }
+        double y = 0.0, un = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            y += nrm[k] * (xe[k] - xc[k]);
+            un += nrm[k] * uel[k];
+        }
+        y = fabs(y);
+        if (!(y > 0.0)) { g_bad_element = f; return -2; }
+        double ut[3], U = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            ut[k] = uel[k] - un * nrm[k];
+            U += ut[k] * ut[k];
+        }
+        U = sqrt(U);
+        const double utau = oracle_friction_velocity(U, y, nu);
+        double t[3] = {0, 0, 0};
+        if (U > 0.0)
+            for (int k = 0; k < 3; ++k) t[k] = -utau * utau * ut[k] / U;
+        for (int b = 0; b < nf; ++b)
+            for (int k = 0; k < 3; ++k) out[3 * ff[b] + k] += t[k] * wa[b];
+        if (diag_y) diag_y[f] = y;
+        if (diag_U) diag_U[f] = U;
+        if (diag_ut) diag_ut[f] = utau;
+    }
+    return 0;
+}

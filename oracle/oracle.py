@@ -58,6 +58,11 @@ def load():
         lib.oracle_element_laplacian.argtypes = [i32, P, P]
         lib.oracle_divergence.argtypes = [i64, P, i64, P, P, P, P, i64, P, P]
         lib.oracle_element_stress_residual.argtypes = [i32, P, P, P]
+        lib.oracle_wall_law.argtypes = [f64]
+        lib.oracle_wall_law.restype = f64
+        lib.oracle_friction_velocity.argtypes = [f64, f64, f64]
+        lib.oracle_friction_velocity.restype = f64
+        lib.oracle_wall_assemble.argtypes = [i64, P, i64, P, P, P, P, i64, P, f64, i64, P, P, P, P, P, P, P]
         lib.oracle_bad_element.restype = ctypes.c_longlong
         _lib = lib
         return lib
@@ -194,3 +199,30 @@ def element_stress_residual(t: int, x, tau) -> np.ndarray:
     R = np.zeros((nnode(t), 3))
     _check(load().oracle_element_stress_residual(t, _p(x), _p(tau), _p(R)))
     return R
+
+
+def wall_law(yp: float) -> float:
+    """Reichardt's law of the wall, u+ as a function of y+."""
+    return load().oracle_wall_law(float(yp))
+
+
+def friction_velocity(U: float, y: float, nu: float) -> float:
+    """u_tau solving U = u_tau f(y u_tau / nu)."""
+    return load().oracle_friction_velocity(float(U), float(y), float(nu))
+
+
+def wall_assemble(mesh, u, nu: float, face_offsets, face_conn, face_elem):
+    """Wall-model nodal contributions [n_field_nodes, 3] (boundary assembly)
+    and per-face diagnostics (y, U, u_tau)."""
+    coords, types, offs, conn, fn, nf = _mesh_args(mesh)
+    u = _f64(u, (nf, 3))
+    fo = np.ascontiguousarray(face_offsets, dtype=np.int64)
+    fc = np.ascontiguousarray(face_conn, dtype=np.int32)
+    fe = np.ascontiguousarray(face_elem, dtype=np.int64)
+    nfaces = len(fe)
+    out = np.zeros((nf, 3))
+    y, U, ut = np.zeros(nfaces), np.zeros(nfaces), np.zeros(nfaces)
+    _check(load().oracle_wall_assemble(len(coords), _p(coords), len(types), _p(types), _p(offs), _p(conn), _p(fn), nf,
+                                       _p(u), float(nu), nfaces, _p(fo), _p(fc), _p(fe), _p(out), _p(y), _p(U),
+                                       _p(ut)))
+    return out, y, U, ut

@@ -92,6 +92,7 @@ const float *mlp_bias(const lesasm_mlp *p);
 int grid_for(size_t n, int block);
 int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, double dt, double *rhs, hipStream_t s,
                   bool increment);
+int launch_wall(lesasm_mesh *m, const double *u, double nu, double *rhs, hipStream_t s);
 
 // Arguments of one assembly launch over a contiguous element range of a category.
 struct CatView {
@@ -144,6 +145,14 @@ struct lesasm_mesh {
     int chunk_max_nodes = 750;              // node cap of a chunk (LDS budget: two workgroups per CU)
     unsigned long long *d_fallbacks = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+    // wall model (boundary assembly): per wall face, the nodes of the face and
+    // of the volume element it bounds, in internal numbering
+    std::vector<int32_t> h_gint, h_fint;  // user geometry node -> internal geometry / field node
+    int64_t n_wall = 0;
+    int32_t *d_wall_fg = nullptr;  // [n_wall][4] face nodes, geometry ids (-1 pads a triangle)
+    int32_t *d_wall_ff = nullptr;  // [n_wall][4] face nodes, field ids
+    int32_t *d_wall_eg = nullptr;  // [n_wall][8] element nodes, geometry ids (-1 pads)
+    int32_t *d_wall_ef = nullptr;  // [n_wall][8] element nodes, field ids
     // profiling: events pending per kernel slot, accumulated times and counts
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[LESASM_NUM_KERNEL_SLOTS];
     double prof_ms[LESASM_NUM_KERNEL_SLOTS] = {0};

@@ -379,6 +379,12 @@ extern "C" const char *lesasm_last_error(void) { return g_error.c_str(); }
 
 extern "C" int lesasm_version(void) { return LESASM_VERSION; }
 
+extern "C" int lesasm_check(void *stream) {
+    LESASM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
 extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) {
     if (!out) return fail(LESASM_E_INVALID_ARG, "mesh_create: out is NULL");
     *out = nullptr;
@@ -507,6 +513,9 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
     }
     m->h_fperm.assign(nf, 0);
     for (int64_t f = 0; f < nf; ++f) m->h_fperm[fnew[f]] = (int32_t)f;
+    m->h_gint = gnew;
+    m->h_fint.assign(nn, 0);
+    for (int64_t g = 0; g < nn; ++g) m->h_fint[g] = fnew[fmap ? fmap[g] : g];
     // without a field map the two numberings coincide, so one index array serves both
     const bool alias = (fmap == nullptr);
 
@@ -709,6 +718,74 @@ extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t 
     case LESASM_OPT_CONCURRENT: *value = m->concurrent; return LESASM_OK;
     default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
     }
+}
+
+extern "C" int lesasm_mesh_set_wall(lesasm_mesh *m, const lesasm_wall_desc *d) {
+    if (!m || !d) return fail(LESASM_E_INVALID_ARG, "set_wall: NULL argument");
+    if (d->n_faces < 0 || (d->n_faces > 0 && (!d->face_offsets || !d->face_conn || !d->face_elem)))
+        return fail(LESASM_E_INVALID_ARG, "set_wall: bad face arrays");
+    if (d->n_faces > INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "set_wall: too many faces");
+    int cur = 0;
+    LESASM_HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) return fail(LESASM_E_STATE, "set_wall: current device differs from the mesh's device");
+    const int64_t F = d->n_faces;
+    std::vector<int32_t> fg(4 * (size_t)F, -1), ff(4 * (size_t)F, -1), eg(8 * (size_t)F, -1), ef(8 * (size_t)F, -1);
+    std::vector<int64_t> einv(m->n_elems, -1);
+    for (int64_t i = 0; i < m->n_elems; ++i) einv[m->h_eperm[i]] = i;
+    if (d->face_offsets[0] != 0) return fail(LESASM_E_INVALID_ARG, "set_wall: face_offsets[0] must be 0");
+    for (int64_t f = 0; f < F; ++f) {
+        const int64_t o = d->face_offsets[f], nfn = d->face_offsets[f + 1] - o;
+        if (nfn != 3 && nfn != 4)
+            return fail(LESASM_E_INVALID_ARG, "set_wall: face " + std::to_string(f) + " has neither 3 nor 4 nodes");
+        for (int64_t b = 0; b < nfn; ++b) {
+            const int32_t g = d->face_conn[o + b];
+            if (g < 0 || g >= m->n_nodes)
+                return fail(LESASM_E_INVALID_ARG, "set_wall: face " + std::to_string(f) + " node out of range");
+            fg[4 * f + b] = m->h_gint[g];
+            ff[4 * f + b] = m->h_fint[g];
+        }
+        const int64_t e = d->face_elem[f];
+        if (e < 0 || e >= m->n_elems)
+            return fail(LESASM_E_INVALID_ARG, "set_wall: face " + std::to_string(f) + " element out of range");
+        const int64_t i = einv[e];
+        int k = 0;
+        while (k < kNumCat - 1 && !(i >= m->cat[k].first && i < m->cat[k].first + m->cat[k].n)) ++k;
+        const Category &c = m->cat[k];
+        const int64_t j = i - c.first;
+        const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
+        for (int a = 0; a < c.type; ++a) {
+            eg[8 * f + a] = c.h_cg[(size_t)a * c.n + j];
+            ef[8 * f + a] = cf[(size_t)a * c.n + j];
+        }
+    }
+    LESASM_HIP_TRY(hipDeviceSynchronize());
+    dfree(m, m->d_wall_fg);
+    dfree(m, m->d_wall_ff);
+    dfree(m, m->d_wall_eg);
+    dfree(m, m->d_wall_ef);
+    m->n_wall = 0;
+    int st;
+    if (F > 0) {
+        if ((st = upload(m, &m->d_wall_fg, fg)) || (st = upload(m, &m->d_wall_ff, ff)) ||
+            (st = upload(m, &m->d_wall_eg, eg)) || (st = upload(m, &m->d_wall_ef, ef)))
+            return st;
+    }
+    m->n_wall = F;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_assemble_wall(lesasm_mesh *m, const double *d_u, double nu, double *d_rhs, void *stream) {
+    if (!m) return fail(LESASM_E_INVALID_ARG, "assemble_wall: mesh is NULL");
+    if (m->n_wall == 0) return LESASM_OK;
+    if (!d_u || !d_rhs) return fail(LESASM_E_INVALID_ARG, "assemble_wall: u or rhs is NULL");
+    if (((uintptr_t)d_u & 7u) || ((uintptr_t)d_rhs & 7u))
+        return fail(LESASM_E_INVALID_ARG, "assemble_wall: pointers must be 8-byte aligned");
+    if (d_rhs == d_u) return fail(LESASM_E_INVALID_ARG, "assemble_wall: rhs aliases u");
+    if (!(nu > 0.0)) return fail(LESASM_E_INVALID_ARG, "assemble_wall: nu must be positive");
+    int cur = 0;
+    LESASM_HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) return fail(LESASM_E_STATE, "assemble_wall: current device differs from the mesh's device");
+    return launch_wall(m, d_u, nu, d_rhs, (hipStream_t)stream);
 }
 
 extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, double delta_ref, double fallback_tol) {

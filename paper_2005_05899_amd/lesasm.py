@@ -29,6 +29,7 @@ EXPORTS = [
     "lesasm_mesh_element_permutation", "lesasm_fields_to_internal", "lesasm_fields_to_user",
     "lesasm_mesh_lumped_mass", "lesasm_mesh_filter_width", "lesasm_mesh_set_option", "lesasm_mesh_get_option",
     "lesasm_assemble_momentum_rhs", "lesasm_mesh_kernel_times", "lesasm_last_error", "lesasm_version",
+    "lesasm_check", "lesasm_mesh_set_wall", "lesasm_assemble_wall",
     "lesasm_divergence", "lesasm_gradient", "lesasm_stepper_create", "lesasm_stepper_destroy", "lesasm_stepper_step",
     "lesasm_stepper_rk3_stages", "lesasm_pressure_solve", "lesasm_stepper_stats", "lesasm_stepper_laplacian",
     "lesasm_batch_create", "lesasm_batch_destroy", "lesasm_batch_configure", "lesasm_batch_get_config",
@@ -54,6 +55,11 @@ class MeshDesc(ctypes.Structure):
         ("field_node", ctypes.c_void_p), ("n_field_nodes", ctypes.c_int64), ("vreman_c", ctypes.c_double),
         ("flags", ctypes.c_uint32),
     ]
+
+
+class WallDesc(ctypes.Structure):
+    _fields_ = [("n_faces", ctypes.c_int64), ("face_offsets", ctypes.c_void_p), ("face_conn", ctypes.c_void_p),
+                ("face_elem", ctypes.c_void_p)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -83,7 +89,8 @@ def load(path: str = LIB_PATH):
         "lesasm_mesh_lumped_mass": [P, P, P], "lesasm_mesh_filter_width": [P, P, P],
         "lesasm_mesh_set_option": [P, I, I64], "lesasm_mesh_get_option": [P, I, P],
         "lesasm_assemble_momentum_rhs": [P, P, P, D, D, P, P], "lesasm_mesh_kernel_times": [P, P, P, I],
-        "lesasm_version": [], "lesasm_divergence": [P, P, P, P], "lesasm_gradient": [P, P, P, P],
+        "lesasm_version": [], "lesasm_check": [P], "lesasm_mesh_set_wall": [P, P],
+        "lesasm_assemble_wall": [P, P, D, P, P], "lesasm_divergence": [P, P, P, P], "lesasm_gradient": [P, P, P, P],
         "lesasm_stepper_create": [P, D, D, D, I, P], "lesasm_stepper_destroy": [P], "lesasm_stepper_step": [P, P, P, P],
         "lesasm_stepper_rk3_stages": [P, P, P, P, P], "lesasm_pressure_solve": [P, P, P, P],
         "lesasm_stepper_stats": [P, P, P], "lesasm_stepper_laplacian": [P, P, P, P, P],
@@ -237,6 +244,20 @@ class Mesh:
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_SLOTS)}
 
     # ---- the hot path --------------------------------------------------------
+    def set_wall(self, face_offsets, face_conn, face_elem):
+        """Wall faces (user node and element ids) for the wall model."""
+        fo = np.ascontiguousarray(face_offsets, dtype=np.int64)
+        fc = np.ascontiguousarray(face_conn, dtype=np.int32)
+        fe = np.ascontiguousarray(face_elem, dtype=np.int64)
+        d = WallDesc(len(fe), fo.ctypes.data, fc.ctypes.data, fe.ctypes.data)
+        check(load().lesasm_mesh_set_wall(self._h, ctypes.byref(d)))
+
+    def assemble_wall(self, u, nu: float, out):
+        """out += wall-model contributions (internal order)."""
+        u = self._field(u)
+        check(load().lesasm_assemble_wall(self._h, _ptr(u), float(nu), _ptr(out), _stream()))
+        return out
+
     def assemble_momentum_rhs(self, u, p=None, nu: float = 0.0, dt: float = 0.0, out=None):
         """rhs [n_field_nodes, 3] (internal order) of M_L du/dt = rhs for velocity
         u [n_field_nodes, 3] and modified pressure p [n_field_nodes] (or None)."""
@@ -301,6 +322,13 @@ class Stepper:
         check(load().lesasm_stepper_laplacian(self._h, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data,
                                               ctypes.byref(nnz)))
         return rowptr, col, val
+
+
+def check_stream(stream=None):
+    """Wait for the stream (default: the current torch stream) and raise if an
+    asynchronous library call failed on it."""
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    check(load().lesasm_check(s))
 
 
 def divergence(mesh: Mesh, u):

@@ -271,6 +271,41 @@ def hybrid_box(nx: int, ny: int, layers, length=(2 * math.pi,) * 3, ratio: float
                       "layer_info": layer_info})
 
 
+# Faces of each element type as cycles of local nodes (topology only).
+FACES = {
+    TET04: [(0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)],
+    PYR05: [(0, 1, 2, 3), (0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)],
+    PEN06: [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)],
+    HEX08: [(0, 1, 2, 3), (4, 5, 6, 7), (0, 1, 5, 4), (1, 2, 6, 5), (2, 3, 7, 6), (3, 0, 4, 7)],
+}
+
+
+def wall_faces(mesh: Mesh, axis: int = 2, value: float = 0.0):
+    """Element faces whose nodes all lie on the plane x[axis] == value (the
+    generators keep boundary nodes exactly on their plane).  Returns
+    (face_offsets int64 [F+1], face_conn int32, face_elem int64 [F]), faces in
+    element order, nodes as a cycle of the element's face."""
+    on = mesh.coords[:, axis] == value
+    elems, conns = [], []
+    for t, faces in FACES.items():
+        idx = np.where(mesh.types == t)[0]
+        if len(idx) == 0:
+            continue
+        en = mesh.conn[mesh.conn_offsets[idx][:, None] + np.arange(t)[None, :]]
+        for f in faces:
+            hit = on[en[:, list(f)]].all(axis=1)
+            for e, nodes in zip(idx[hit], en[hit][:, list(f)]):
+                elems.append(int(e))
+                conns.append(nodes)
+    order = np.argsort(np.asarray(elems, dtype=np.int64), kind="stable")
+    elems = np.asarray(elems, dtype=np.int64)[order]
+    conns = [conns[i] for i in order]
+    offs = np.zeros(len(conns) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(c) for c in conns])
+    flat = np.concatenate(conns).astype(np.int32) if conns else np.zeros(0, np.int32)
+    return offs, flat, elems
+
+
 def hybrid_layers(n_cells_xy: int, target_elems: int, fractions=None) -> list:
     """Whole cell layers per type (wall first: PEN06, TET04, PYR05, HEX08) whose
     element counts come closest to ``fractions`` of ``target_elems``."""

@@ -178,6 +178,22 @@ def test_empty_mesh(torch_cuda):
     m.close()
 
 
+def test_check_reports_clean_stream(torch_cuda, small):
+    """lesasm_check waits for the stream and returns OK after good work."""
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    c, _ = small
+    m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+    u = m.to_internal(torch.from_numpy(c.u).cuda())
+    m.assemble_momentum_rhs(u, None, c.nu)
+    lesasm.check_stream()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        m.assemble_momentum_rhs(u, None, c.nu)
+    lesasm.check_stream(s.cuda_stream)
+    m.close()
+
+
 def test_lumped_mass_and_filter_width(torch_cuda, small):
     import oracle
     torch = torch_cuda

@@ -12,7 +12,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lesasm_oracle.c")
 PINS = ["tests/test_oracle_refelem.py", "tests/test_oracle_vreman.py", "tests/test_oracle_exact.py",
-        "tests/test_oracle_invariants.py", "tests/test_oracle_step.py", "tests/test_oracle_closure.py"]
+        "tests/test_oracle_invariants.py", "tests/test_oracle_step.py", "tests/test_oracle_closure.py",
+        "tests/test_oracle_wall.py"]
 
 MUTANTS = {
     "gradient_uses_J_inverse_untransposed": ("s += K[j][i] * dN[3 * a + j];", "s += K[i][j] * dN[3 * a + j];"),
@@ -37,6 +38,14 @@ MUTANTS = {
     "laplacian_drops_jacobian": ("K[a * n + b] += w[q] * det * s;", "K[a * n + b] += w[q] * s;"),
     "divergence_untransposed_inverse": ("div += ue[3 * a + i] * Ki[j][i] * dN[3 * a + j];",
                                         "div += ue[3 * a + i] * Ki[i][j] * dN[3 * a + j];"),
+    "wall_traction_sign": ("t[k] = -utau * utau * ut[k] / U;", "t[k] = utau * utau * ut[k] / U;"),
+    "wall_keeps_normal_velocity": ("ut[k] = uel[k] - un * nrm[k];", "ut[k] = uel[k];"),
+    "wall_law_drops_damping": ("WALL_C1 * (1.0 - exp(-yp / WALL_CHI) - (yp / WALL_CHI) * exp(-yp / 3.0));",
+                               "WALL_C1 * (1.0 - exp(-yp / WALL_CHI));"),
+    "wall_quad_drops_jacobian": ("wa[a] += 0.25 * (1.0 + s[a] * xi) * (1.0 + t[a] * eta) * jac;",
+                                 "wa[a] += 0.25 * (1.0 + s[a] * xi) * (1.0 + t[a] * eta);"),
+    "wall_distance_from_origin": ("y += nrm[k] * (xe[k] - xc[k]);", "y += nrm[k] * xe[k];"),
+    "wall_tau_not_squared": ("t[k] = -utau * utau * ut[k] / U;", "t[k] = -utau * ut[k] / U;"),
 }
 
 
