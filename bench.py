@@ -71,11 +71,16 @@ def per_type_bytes(mesh, t: int) -> float:
 
 
 def field_errors(got, ref) -> dict:
+    """Per component relative L2 and max errors (absolute ones where the
+    reference component is identically zero)."""
     out = {}
     for i, name in enumerate("xyz"):
         d = got[:, i] - ref[:, i]
-        out[f"u{name}"] = {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref[:, i])),
-                           "rel_max": float(np.abs(d).max() / np.abs(ref[:, i]).max())}
+        nr, mr = np.linalg.norm(ref[:, i]), np.abs(ref[:, i]).max()
+        if nr > 0:
+            out[f"u{name}"] = {"rel_l2": float(np.linalg.norm(d) / nr), "rel_max": float(np.abs(d).max() / mr)}
+        else:
+            out[f"u{name}"] = {"abs_l2": float(np.linalg.norm(d)), "abs_max": float(np.abs(d).max())}
     return out
 
 

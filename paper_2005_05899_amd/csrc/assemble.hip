@@ -134,9 +134,11 @@ static void launch_chunk_kernel(const ChunkView &v, int n_chunks, size_t shm, co
                                 double cv, double *rhs) {
     const dim3 grid(n_chunks), blk(block);
     if (cl) {
-        const size_t shm_mlp = shm + kMlpLdsBytes + (size_t)(block / 64) * kMlpWaveScratch;
+        // network block after the node data, 16-byte aligned (vector reads of the biases)
+        const size_t node_doubles = (shm / sizeof(double) + 1) & ~(size_t)1;
+        const size_t shm_mlp = node_doubles * sizeof(double) + kMlpLdsBytes + (size_t)(block / 64) * kMlpWaveScratch;
         hipLaunchKernelGGL((k_assemble_chunk_mlp<T, R, HAS_P, PERIODIC, STAGED>), grid, blk, shm_mlp, s, v, xyz, u, p,
-                           nu, cv, rhs, *cl, (int)(shm / sizeof(double)));
+                           nu, cv, rhs, *cl, (int)node_doubles);
     } else {
         hipLaunchKernelGGL((k_assemble_chunk<T, R, HAS_P, PERIODIC, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv,
                            rhs);

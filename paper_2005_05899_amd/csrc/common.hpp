@@ -65,8 +65,8 @@ struct Category {
     int32_t *d_gnodes = nullptr;   // geometry nodes of each chunk, ascending
     int32_t *d_foff = nullptr;     // [n_chunks+1] offsets into d_fnodes (aliases d_goff without a field map)
     int32_t *d_fnodes = nullptr;   // field nodes of each chunk; bit 31 set if the chunk owns the node
-    uint16_t *d_lg = nullptr;      // [n][8] chunk-local geometry index of each element node (16-byte records)
-    uint16_t *d_lf = nullptr;      // [n][8] chunk-local field index (aliases d_lg without a field map)
+    uint16_t *d_lg = nullptr;      // [nnode][n] chunk-local geometry index of each element slot
+    uint16_t *d_lf = nullptr;      // [nnode][n] chunk-local field index (aliases d_lg without a field map)
     int32_t *d_fslot = nullptr;    // per d_fnodes entry: staging slot of a shared node, -1 if owned
     int lds_doubles = 0;           // largest LDS footprint of a chunk, in doubles
     int chunk_elems = 0;           // chunk length used for this category
@@ -77,7 +77,7 @@ struct Category {
 // Arguments of one chunked launch (one workgroup per chunk).
 struct ChunkView {
     const int32_t *eoff, *goff, *gnodes, *foff, *fnodes, *fslot;
-    const uint16_t *lg, *lf;  // [n][8] local slots per element (16-byte records)
+    const uint16_t *lg, *lf;
     const double *delta;
     double *stage;  // staging rows [slot][3] for shared nodes
     int32_t ld;     // elements in the category
@@ -142,7 +142,7 @@ struct lesasm_mesh {
     // learned closure (NULL: Vreman)
     const lesasm_mlp *mlp = nullptr;
     double delta_ref = 1.0, fallback_tol = 0.05;
-    int chunk_max_nodes = 750;              // node cap of a chunk (LDS budget: two workgroups per CU)
+    int chunk_max_nodes = 800;              // node cap of a chunk (LDS budget)
     unsigned long long *d_fallbacks = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     // wall model (boundary assembly): per wall face, the nodes of the face and

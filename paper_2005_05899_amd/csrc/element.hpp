@@ -16,6 +16,10 @@
 #include "mlp.hpp"
 #include "modal.hpp"
 
+#ifndef LESASM_SPREAD_WAVES
+#define LESASM_SPREAD_WAVES 1
+#endif
+
 namespace lesasm {
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
@@ -114,32 +118,18 @@ __device__ __forceinline__ void gather(ElementData<T, R> &d, const CatView &c, i
         [&](int a, int k) { return u[3 * (size_t)d.fid[a] + k]; }, [&](int a) { return p[d.fid[a]]; });
 }
 
-// Element data from chunk-staged LDS records of 32 bytes: coordinates
-// sx[k] = (x, y, z, -) by local geometry slot, velocity and pressure
-// su[k] = (u, v, w, p) by local field slot; each record is two 16-byte reads.
+// Element data from chunk-staged LDS arrays: node coordinates sx[k][3] by
+// local geometry slot, velocity su[k][3] and pressure sp[k] by local field slot.
 template <int T, typename R, bool HAS_P>
 __device__ __forceinline__ void gather_lds(ElementData<T, R> &d, const int (&lg)[Ref<T>::nn],
-                                           const int (&lf)[Ref<T>::nn], const double *sx, const double *su) {
+                                           const int (&lf)[Ref<T>::nn], const double *sx, const double *su,
+                                           const double *sp) {
     constexpr int nn = Ref<T>::nn;
-    double xv[nn][3], uv[nn][3], pv[nn];
 #pragma unroll
-    for (int a = 0; a < nn; ++a) {
-        d.fid[a] = lf[a];
-        const double2 *px = (const double2 *)(sx + 4 * lg[a]);
-        const double2 x01 = px[0], x2 = px[1];
-        xv[a][0] = x01.x;
-        xv[a][1] = x01.y;
-        xv[a][2] = x2.x;
-        const double2 *pu = (const double2 *)(su + 4 * lf[a]);
-        const double2 u01 = pu[0], u2p = pu[1];
-        uv[a][0] = u01.x;
-        uv[a][1] = u01.y;
-        uv[a][2] = u2p.x;
-        pv[a] = u2p.y;
-    }
+    for (int a = 0; a < nn; ++a) d.fid[a] = lf[a];
     load_element<T, R, HAS_P>(
-        d, [&](int a, int k) { return xv[a][k]; }, [&](int a, int k) { return uv[a][k]; },
-        [&](int a) { return pv[a]; });
+        d, [&](int a, int k) { return sx[3 * lg[a] + k]; }, [&](int a, int k) { return su[3 * lf[a] + k]; },
+        [&](int a) { return sp[lf[a]]; });
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates refined
@@ -429,10 +419,9 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 // chunk's distinct nodes are loaded once into LDS (coordinates, velocity,
 // pressure), every element reads them from there, and element residuals are
 // summed into per-node LDS accumulators.  Afterwards each node is written once:
-// a plain store when every element touching it lies in this chunk (owned), a
-// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout:
-//   (x, y, z, -)[ng] | (u, v, w, p)[nf] | acc[nf][3] doubles, then 16-byte
-//   element records: geometry slots [ne], field slots [ne] (periodic), widths.
+// a plain store when every element touching it lies in this chunk (owned), an
+// staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
+//   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
 // Learned closure of a launch: packed weights, filter-width reference and
 // the fallback threshold (squared), plus a counter of Vreman fallbacks.
 struct ClosureView {
@@ -442,13 +431,6 @@ struct ClosureView {
     double tol2;
     unsigned long long *fallbacks;
 };
-
-// The first n 16-bit slots of a 16-byte element record.
-template <int N> __device__ __forceinline__ void unpack_slots(const uint4 r, int (&s)[N]) {
-    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-    for (int a = 0; a < N; ++a) s[a] = (int)((w[a >> 1] >> (16 * (a & 1))) & 0xffffu);
-}
 
 template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED, bool MLP = false>
 __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *lds, const double *__restrict__ xyz,
@@ -460,46 +442,48 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
     const int g0 = c.goff[j], ng = c.goff[j + 1] - g0;
     const int f0 = PERIODIC ? c.foff[j] : g0;
     const int nf = PERIODIC ? c.foff[j + 1] - f0 : ng;
-    double *sx = lds, *su = sx + 4 * ng, *sacc = su + 4 * nf;
-    // element records after the node records (16-byte aligned): local geometry
-    // slots, local field slots (periodic meshes), filter widths
-    const int ne = e1 - e0;
-    uint4 *sig = (uint4 *)(lds + ((4 * ng + 7 * nf + 1) & ~1));
-    uint4 *sif = PERIODIC ? sig + ne : sig;
-    double *sdl = (double *)(sig + (PERIODIC ? 2 * ne : ne));
+    double *sx = lds, *su = sx + 3 * ng, *sp = su + 3 * nf, *sacc = sp + nf;
 
     for (int k = threadIdx.x; k < ng; k += blockDim.x) {
         const size_t g = (size_t)c.gnodes[g0 + k];
-        double2 *dst = (double2 *)(sx + 4 * k);
-        dst[0] = make_double2(xyz[3 * g + 0], xyz[3 * g + 1]);
-        dst[1] = make_double2(xyz[3 * g + 2], 0.0);
+        sx[3 * k + 0] = xyz[3 * g + 0];
+        sx[3 * k + 1] = xyz[3 * g + 1];
+        sx[3 * k + 2] = xyz[3 * g + 2];
     }
     for (int k = threadIdx.x; k < nf; k += blockDim.x) {
         const size_t f = (size_t)((uint32_t)c.fnodes[f0 + k] & ~kOwnedBit);
-        double2 *dst = (double2 *)(su + 4 * k);
-        dst[0] = make_double2(u[3 * f + 0], u[3 * f + 1]);
-        dst[1] = make_double2(u[3 * f + 2], HAS_P ? p[f] : 0.0);
+        su[3 * k + 0] = u[3 * f + 0];
+        su[3 * k + 1] = u[3 * f + 1];
+        su[3 * k + 2] = u[3 * f + 2];
+        sp[k] = HAS_P ? p[f] : 0.0;
         sacc[3 * k + 0] = sacc[3 * k + 1] = sacc[3 * k + 2] = 0.0;
-    }
-    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
-        sig[k] = ((const uint4 *)c.lg)[e0 + k];
-        if (PERIODIC) sif[k] = ((const uint4 *)c.lf)[e0 + k];
-        sdl[k] = c.delta[e0 + k];
     }
     if constexpr (MLP) mlp_stage(cl->packed, cl->bias, (unsigned char *)(lds + lds_node_doubles));
     __syncthreads();
 
     if constexpr (!MLP) {
-        for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        for (int base = e0; base < e1; base += blockDim.x) {
+#if LESASM_SPREAD_WAVES
+            // In a full block, wavefront w takes every (blockDim/64)-th element
+            // starting at w: neighbouring elements (which share nodes) go to
+            // different wavefronts, so fewer lanes of one LDS atomic hit the
+            // same node.
+            const int e = base + (int)blockDim.x <= e1
+                              ? base + (int)(threadIdx.x & 63) * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6)
+                              : base + (int)threadIdx.x;
+#else
+            const int e = base + (int)threadIdx.x;
+#endif
+            if (e >= e1) break;
             int lg[nn], lf[nn];
-            unpack_slots<nn>(sig[e - e0], lg);
-            if (PERIODIC) unpack_slots<nn>(sif[e - e0], lf);
-            else
 #pragma unroll
-                for (int a = 0; a < nn; ++a) lf[a] = lg[a];
-            const double dl = sdl[e - e0];
+            for (int a = 0; a < nn; ++a) {
+                lg[a] = c.lg[(size_t)a * c.ld + e];
+                lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+            }
             ElementData<T, R> d;
-            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su);
+            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+            const double dl = c.delta[e];
             R acc[nn][3];
             element_residual<T, R, HAS_P>(d, (R)nu, (R)(cv * dl * dl), acc);
 #pragma unroll
@@ -524,14 +508,14 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
             const bool active = base + (int)threadIdx.x < e1;
             const int e = active ? base + (int)threadIdx.x : e1 - 1;
             int lg[nn], lf[nn];
-            unpack_slots<nn>(sig[e - e0], lg);
-            if (PERIODIC) unpack_slots<nn>(sif[e - e0], lf);
-            else
 #pragma unroll
-                for (int a = 0; a < nn; ++a) lf[a] = lg[a];
+            for (int a = 0; a < nn; ++a) {
+                lg[a] = c.lg[(size_t)a * c.ld + e];
+                lf[a] = PERIODIC ? (int)c.lf[(size_t)a * c.ld + e] : lg[a];
+            }
             ElementData<T, R> d;
-            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su);
-            const double dl = sdl[e - e0];
+            gather_lds<T, R, HAS_P>(d, lg, lf, sx, su, sp);
+            const double dl = c.delta[e];
             mc.logd = (float)(log(dl) - cl->log_delta_ref);
             R acc[nn][3], dacc[nn][3];
             element_residual<T, R, HAS_P, true>(d, (R)nu, (R)(cv * dl * dl), acc, (R)(dl * dl), dacc, &mc);

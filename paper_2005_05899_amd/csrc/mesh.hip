@@ -190,8 +190,8 @@ template <class T> static void dfree(lesasm_mesh *m, T *&p) {
 
 // Chunks for the chunked scatter of category k: runs of consecutive internal
 // elements, at most m->chunk_elems long and with at most m->chunk_max_nodes
-// distinct geometry and field nodes (750, or 400 when the learned closure
-// also needs LDS), so that a chunk's node and element data fit in LDS.  Node
+// distinct geometry and field nodes (800, or 400 when the learned closure
+// also needs LDS), so that a chunk's node data fit in LDS.  Node
 // lists are sorted ascending (coalesced loads); a field node is owned by a
 // chunk when all of its incidences in the mesh lie in that chunk.
 
@@ -225,7 +225,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
     const int ce = chunk_length(m, n);
     c.chunk_elems = ce;
     std::vector<int32_t> eoff{0}, goff{0}, foff{0}, gnodes, fnodes;
-    std::vector<uint16_t> lg((size_t)8 * n, 0), lf(periodic ? (size_t)8 * n : 0, 0);
+    std::vector<uint16_t> lg((size_t)nnode * n), lf(periodic ? (size_t)nnode * n : 0);
     std::vector<int32_t> gslot(m->n_nodes, -1), fslot(m->n_field, -1), fcount(m->n_field, 0);
     std::vector<int32_t> gl, fl;
     int64_t start = 0;
@@ -256,8 +256,8 @@ static int build_chunks(lesasm_mesh *m, int k) {
         for (int64_t x = start; x < e; ++x)
             for (int a = 0; a < nnode; ++a) {
                 const size_t s = (size_t)a * n + x;
-                lg[8 * (size_t)x + a] = (uint16_t)gslot[cg[s]];
-                if (periodic) lf[8 * (size_t)x + a] = (uint16_t)fslot[cf[s]];
+                lg[s] = (uint16_t)gslot[cg[s]];
+                if (periodic) lf[s] = (uint16_t)fslot[cf[s]];
             }
         for (int32_t g : gl) {
             gnodes.push_back(g);
@@ -268,10 +268,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
             fcount[f] = 0;
             fslot[f] = -1;
         }
-        // node records, then (16-byte aligned) the element index records and widths
-        const int node_doubles = (int)(4 * gl.size() + 7 * fl.size());
-        const int ne = (int)(e - start);
-        c.lds_doubles = std::max(c.lds_doubles, ((node_doubles + 1) & ~1) + (periodic ? 4 : 2) * ne + ne);
+        c.lds_doubles = std::max(c.lds_doubles, (int)(3 * gl.size() + 7 * fl.size()));
         eoff.push_back((int32_t)e);
         goff.push_back((int32_t)gnodes.size());
         foff.push_back((int32_t)fnodes.size());
@@ -805,7 +802,7 @@ extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, do
     m->mlp = mlp;
     m->delta_ref = mlp ? delta_ref : 1.0;
     m->fallback_tol = mlp ? fallback_tol : 0.05;
-    const int cap = mlp ? 400 : 750;
+    const int cap = mlp ? 400 : 800;
     if (cap != m->chunk_max_nodes) {
         m->chunk_max_nodes = cap;
         return build_scatter(m);

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(128) void k_mlp_forward_f32(const float *__restrict
 __global__ __launch_bounds__(256) void k_mlp_infer_bf16(const short *__restrict__ packed,
                                                         const float *__restrict__ bias, const float *__restrict__ X,
                                                         int n, float *__restrict__ Y) {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem[];
     const MlpLds w = mlp_stage(packed, bias, smem);
     __syncthreads();
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;

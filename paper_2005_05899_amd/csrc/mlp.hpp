@@ -54,10 +54,29 @@ __device__ __forceinline__ MlpLds mlp_stage(const short *__restrict__ packed, co
     return MlpLds{(const bf16x4_t *)t, b, b + kMlpH, b + 2 * kMlpH};
 }
 
+// Two floats to two bf16 (round to nearest even, the hardware conversion),
+// packed low-first into 32 bits.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+__device__ __forceinline__ bf16x4_t pack_bf16x4(float a, float b, float c, float d) {
+    const uint32_t lo = pack_bf16(a, b), hi = pack_bf16(c, d);
+    typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+    const u32x2_t v = {lo, hi};
+    return __builtin_bit_cast(bf16x4_t, v);
+}
+// max(v, 0) as one median-of-three instruction (finite inputs)
+__device__ __forceinline__ float relu(float v) { return __builtin_amdgcn_fmed3f(v, 0.f, 3.0e38f); }
+
 // Whole-wavefront evaluation: every lane supplies the 10 inputs of its own
 // sample and receives its 6 outputs.  All 64 lanes must call it together
 // (matrix instructions ignore the execution mask).  scratch: kMlpWaveScratch
-// bytes of LDS private to this wavefront.
+// bytes of LDS private to this wavefront.  Biases enter as the accumulator
+// input of the first matrix instruction of each tile; layer 2 and layer 3 run
+// row tile by row tile, so only one row tile of H2 is ever held.
 __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpIn], float (&y)[kMlpOut],
                                          unsigned char *scratch) {
     const int lane = __lane_id();
@@ -65,16 +84,15 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
     short *xs = (short *)scratch;                 // [64][16]
     float *ys = (float *)(scratch + 64 * 16 * 2);  // [64][8]
     {
-        bf16x4_t v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = 4 * q + t;
-                v[q][t] = k < kMlpIn ? f2bf(x[k]) : (short)0;
-            }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ((bf16x4_t *)(xs + 16 * lane))[q] = v[q];
+        const bf16x4_t v0 = pack_bf16x4(x[0], x[1], x[2], x[3]);
+        const bf16x4_t v1 = pack_bf16x4(x[4], x[5], x[6], x[7]);
+        const bf16x4_t v2 = pack_bf16x4(x[8], x[9], 0.f, 0.f);
+        const bf16x4_t v3 = {0, 0, 0, 0};
+        bf16x4_t *dst = (bf16x4_t *)(xs + 16 * lane);
+        dst[0] = v0;
+        dst[1] = v1;
+        dst[2] = v2;
+        dst[3] = v3;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -88,24 +106,26 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const bf16x4_t a = w.tiles[mt * 64 + lane];
+        const f32x4_t b = *(const f32x4_t *)(w.b1 + 16 * mt + 4 * lq);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bx[nt], acc, 0, 0, 0);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float v = acc[t] + w.b1[16 * mt + 4 * lq + t];
-                h1[mt][nt][t] = f2bf(v > 0.f ? v : 0.f);
-            }
+            const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bx[nt], b, 0, 0, 0);
+            h1[mt][nt] = pack_bf16x4(relu(acc[0]), relu(acc[1]), relu(acc[2]), relu(acc[3]));
         }
     }
-    // layer 2: H2^T = relu(W2^T H1^T + b2)
-    bf16x4_t h2[4][4];
+    // layers 2 and 3 by row tile of H2: H2^T = relu(W2^T H1^T + b2), Y^T += W3^T H2^T
+    f32x4_t acc3[4];
+    {
+        const f32x4_t b3 = lq < 2 ? *(const f32x4_t *)(w.b3 + 4 * lq) : f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc3[nt] = b3;
+    }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
+        const f32x4_t b = *(const f32x4_t *)(w.b2 + 16 * mt + 4 * lq);
         f32x4_t acc[4];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = b;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const bf16x4_t a = w.tiles[(4 + 4 * mt + ks) * 64 + lane];
@@ -113,29 +133,23 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
             for (int nt = 0; nt < 4; ++nt)
                 acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[ks][nt], acc[nt], 0, 0, 0);
         }
+        const bf16x4_t a3 = w.tiles[(20 + mt) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const bf16x4_t h2 = pack_bf16x4(relu(acc[nt][0]), relu(acc[nt][1]), relu(acc[nt][2]), relu(acc[nt][3]));
+            acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, h2, acc3[nt], 0, 0, 0);
+        }
+    }
+    // Y^T rows 0..5 (lanes with lq < 2 hold rows 0..7)
+    if (lq < 2)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float v = acc[nt][t] + w.b2[16 * mt + 4 * lq + t];
-                h2[mt][nt][t] = f2bf(v > 0.f ? v : 0.f);
-            }
-    }
-    // layer 3: Y^T = W3^T H2^T + b3 (rows 0..5 of one tile)
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w.tiles[(20 + ks) * 64 + lane], h2[ks][nt], acc, 0, 0, 0);
-        if (lq < 2)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) ys[8 * (16 * nt + lr) + 4 * lq + t] = acc[t];
-    }
+            for (int t = 0; t < 4; ++t) ys[8 * (16 * nt + lr) + 4 * lq + t] = acc3[nt][t];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-    for (int o = 0; o < kMlpOut; ++o) y[o] = ys[8 * lane + o] + w.b3[o];
+    for (int o = 0; o < kMlpOut; ++o) y[o] = ys[8 * lane + o];
     __builtin_amdgcn_wave_barrier();
 }
 
