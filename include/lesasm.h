@@ -161,6 +161,10 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
 #define LESASM_OPT_CONCURRENT 7   /* 1 (default): the element-type kernels of one chunked assembly run
                                      concurrently on forked streams (joined before return); 0: one
                                      after another on the caller's stream (isolated kernel timings) */
+#define LESASM_OPT_PERSISTENT 8   /* 0 (default): one workgroup per chunk; 1: the chunk kernels launch
+                                     as many workgroups as the GPU holds at once, each looping over
+                                     chunks (measured slower: it blocks the concurrent type kernels);
+                                     N > 1: at most N workgroups (testing) */
 
 #define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
 #define LESASM_PREC_FP32 1 /* element contractions in FP32 on coefficients formed in FP64

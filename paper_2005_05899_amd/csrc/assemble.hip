@@ -40,14 +40,19 @@ __global__ __launch_bounds__(256) void k_assemble(CatView c, const double *__res
         }
 }
 
-// Chunked scatters: one workgroup per chunk (see chunk_body).
+// Chunked scatters (see chunk_body).  Workgroup w processes chunks w, w + G,
+// w + 2G, ... of the G workgroups launched: one chunk each by default
+// (G = number of chunks), several with a smaller grid.
 template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
-__global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, const double *__restrict__ xyz,
+__global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, int n_chunks, const double *__restrict__ xyz,
                                                         const double *__restrict__ u,
                                                         const double *__restrict__ p, double nu, double cv,
                                                         double *__restrict__ rhs) {
     extern __shared__ __align__(16) double lds[];
-    chunk_body<T, R, HAS_P, PERIODIC, STAGED>(c, xcd_block(blockIdx.x, gridDim.x), lds, xyz, u, p, nu, cv, rhs);
+    for (int j = xcd_block(blockIdx.x, gridDim.x); j < n_chunks; j += gridDim.x) {
+        chunk_body<T, R, HAS_P, PERIODIC, STAGED>(c, j, lds, xyz, u, p, nu, cv, rhs);
+        __syncthreads();  // the next chunk's staging overwrites the LDS
+    }
 }
 
 // The same with the learned closure (network weights after the node data in LDS).
@@ -130,8 +135,8 @@ static void dispatch_scatter(const CatView &v, bool atomic, bool has_p, int bloc
 
 template <int T, typename R, bool STAGED, bool HAS_P, bool PERIODIC>
 static void launch_chunk_kernel(const ChunkView &v, int n_chunks, size_t shm, const ClosureView *cl, int block,
-                                hipStream_t s, const double *xyz, const double *u, const double *p, double nu,
-                                double cv, double *rhs) {
+                                int persist, hipStream_t s, const double *xyz, const double *u, const double *p,
+                                double nu, double cv, double *rhs) {
     const dim3 grid(n_chunks), blk(block);
     if (cl) {
         // network block after the node data, 16-byte aligned (vector reads of the biases)
@@ -140,36 +145,47 @@ static void launch_chunk_kernel(const ChunkView &v, int n_chunks, size_t shm, co
         hipLaunchKernelGGL((k_assemble_chunk_mlp<T, R, HAS_P, PERIODIC, STAGED>), grid, blk, shm_mlp, s, v, xyz, u, p,
                            nu, cv, rhs, *cl, (int)node_doubles);
     } else {
-        hipLaunchKernelGGL((k_assemble_chunk<T, R, HAS_P, PERIODIC, STAGED>), grid, blk, shm, s, v, xyz, u, p, nu, cv,
-                           rhs);
+        auto kern = k_assemble_chunk<T, R, HAS_P, PERIODIC, STAGED>;
+        int g = n_chunks;
+        if (persist > 0) {  // as many workgroups as the GPU holds at once (persist = n_cu), or at most -persist
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, shm) == hipSuccess &&
+                per_cu > 0)
+                g = std::min(n_chunks, per_cu * persist);
+            else
+                (void)hipGetLastError();
+        } else if (persist < 0) {
+            g = std::min(n_chunks, -persist);
+        }
+        hipLaunchKernelGGL(kern, dim3(g), blk, shm, s, v, n_chunks, xyz, u, p, nu, cv, rhs);
     }
 }
 
 template <int T, typename R, bool STAGED>
 static void launch_chunks(const ChunkView &v, int n_chunks, size_t shm, const ClosureView *cl, bool has_p,
-                          bool periodic, int block, hipStream_t s, const double *xyz, const double *u,
+                          bool periodic, int block, int persist, hipStream_t s, const double *xyz, const double *u,
                           const double *p, double nu, double cv, double *rhs) {
     if (periodic) {
-        if (has_p) launch_chunk_kernel<T, R, STAGED, true, true>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
-        else launch_chunk_kernel<T, R, STAGED, false, true>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
+        if (has_p) launch_chunk_kernel<T, R, STAGED, true, true>(v, n_chunks, shm, cl, block, persist, s, xyz, u, p, nu, cv, rhs);
+        else launch_chunk_kernel<T, R, STAGED, false, true>(v, n_chunks, shm, cl, block, persist, s, xyz, u, p, nu, cv, rhs);
     } else {
-        if (has_p) launch_chunk_kernel<T, R, STAGED, true, false>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
-        else launch_chunk_kernel<T, R, STAGED, false, false>(v, n_chunks, shm, cl, block, s, xyz, u, p, nu, cv, rhs);
+        if (has_p) launch_chunk_kernel<T, R, STAGED, true, false>(v, n_chunks, shm, cl, block, persist, s, xyz, u, p, nu, cv, rhs);
+        else launch_chunk_kernel<T, R, STAGED, false, false>(v, n_chunks, shm, cl, block, persist, s, xyz, u, p, nu, cv, rhs);
     }
 }
 
 template <typename R, bool STAGED>
 static void dispatch_chunks(const Category &c, double *stage, const ClosureView *cl, bool has_p, bool periodic,
-                            int block, hipStream_t s, const double *xyz, const double *u, const double *p, double nu,
+                            int block, int persist, hipStream_t s, const double *xyz, const double *u, const double *p, double nu,
                             double cv, double *rhs) {
     ChunkView v{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_fslot, c.d_lg, c.d_lf, c.d_delta, stage,
                 (int32_t)c.n};
     const size_t shm = sizeof(double) * (size_t)c.lds_doubles;
     switch (c.type) {
-    case LESASM_TET04: launch_chunks<LESASM_TET04, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
-    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_TET04: launch_chunks<LESASM_TET04, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, persist, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PYR05: launch_chunks<LESASM_PYR05, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, persist, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_PEN06: launch_chunks<LESASM_PEN06, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, persist, s, xyz, u, p, nu, cv, rhs); break;
+    case LESASM_HEX08: launch_chunks<LESASM_HEX08, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, persist, s, xyz, u, p, nu, cv, rhs); break;
     }
 }
 
@@ -236,11 +252,11 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
         const bool periodic = c.d_lf != c.d_lg;
         const bool f32 = m->precision == LESASM_PREC_FP32;
         if (staged) {
-            if (f32) dispatch_chunks<float, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else dispatch_chunks<double, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            if (f32) dispatch_chunks<float, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else dispatch_chunks<double, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
         } else {
-            if (f32) dispatch_chunks<float, false>(c, nullptr, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            if (f32) dispatch_chunks<float, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
         }
     }
     for (int i = 0; i < (m->concurrent ? std::min(used - 1, 3) : 0); ++i) {

@@ -128,6 +128,8 @@ struct lesasm_mesh {
     int block = 256;
     int profile = 0;
     int concurrent = 1;  // element-type kernels on forked streams
+    int persist = 0;     // chunk kernels: 0 one workgroup per chunk, 1 resident workgroups, N > 1 at most N
+    int n_cu = 0;        // compute units of the mesh's device
     int chunk_elems = 0;            // elements per chunk of the chunked scatter (0: per-type heuristic)
     std::vector<int32_t> h_finc;    // incidences per internal field node (all types)
     // staged scatter: shared nodes get one staging row per chunk touching them;

@@ -426,6 +426,7 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
     lesasm_mesh *m = new lesasm_mesh();
     MeshGuard guard{m};
     LESASM_HIP_TRY(hipGetDevice(&m->device));
+    LESASM_HIP_TRY(hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device));
     m->flags = d->flags;
     m->n_nodes = nn;
     m->n_field = nf;
@@ -687,6 +688,10 @@ extern "C" int lesasm_mesh_set_option(lesasm_mesh *m, int option, int64_t value)
     case LESASM_OPT_CONCURRENT:
         m->concurrent = value != 0;
         return LESASM_OK;
+    case LESASM_OPT_PERSISTENT:
+        if (value < 0 || value > INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "set_option: persistent must be >= 0");
+        m->persist = (int)value;
+        return LESASM_OK;
     case LESASM_OPT_CHUNK: {
         if (value != 0 && (value < 32 || value > 4096))
             return fail(LESASM_E_UNSUPPORTED, "set_option: chunk must be 0 or in 32..4096");
@@ -713,6 +718,7 @@ extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t 
     case LESASM_OPT_PROFILE: *value = m->profile; return LESASM_OK;
     case LESASM_OPT_CHUNK: *value = m->chunk_elems; return LESASM_OK;
     case LESASM_OPT_CONCURRENT: *value = m->concurrent; return LESASM_OK;
+    case LESASM_OPT_PERSISTENT: *value = m->persist; return LESASM_OK;
     default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
     }
 }

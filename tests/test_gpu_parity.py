@@ -102,6 +102,22 @@ def test_chunk_sizes(torch_cuda, small, periodic, chunk, scatter):
         m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("persist", [0, 1, 3])
+def test_persistent_chunk_loop(torch_cuda, small, periodic, persist, precision):
+    """Workgroups looping over chunks: one workgroup per chunk (0), as many as
+    the GPU holds (1), and three workgroups that each process many chunks (3),
+    with short chunks so that every workgroup loops."""
+    from paper_2005_05899_amd import lesasm
+    tol = TOL64 if precision == "fp64" else TOL32
+    for c, ref in (small, periodic):
+        m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+        m.set_option(lesasm.OPT_PERSISTENT, persist)
+        got, m = run_gpu(torch_cuda, c, chunk=32, mesh=m, precision=precision)
+        assert_close(got, ref, tol, f"{c.name} persist={persist} {precision}")
+        m.close()
+
+
 def test_staged_scatter_overwrites_every_node(torch_cuda, small):
     """No zero-fill in the staged scatter: every node is stored exactly once,
     so a NaN-filled output buffer must come back fully overwritten."""
