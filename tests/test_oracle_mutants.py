@@ -74,3 +74,47 @@ def test_pins_catch_mutant(name, tmp_path):
     assert src.count(old) >= 1, name  # every copy of the line gets the same bug
     r = _run_pins(src.replace(old, new), tmp_path)
     assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
+
+
+# ---- the partitioner and balancing oracle (Python) ----------------------------
+
+PART_SRC = os.path.join(ROOT, "oracle", "partition.py")
+PART_PINS = "tests/test_oracle_partition.py"
+PART_MUTANTS = {
+    "hilbert_gray_code_skips_an_axis": ("X[2] = X[2] ^ X[1]", "X[2] = X[2] ^ X[0]"),
+    "hilbert_no_inversion": ("x0_flipped = X[0] ^ low", "x0_flipped = X[0]"),
+    "hilbert_excess_from_first_axis": ("t = np.where((X[2] & q) != 0, t ^ (q - 1), t)",
+                                       "t = np.where((X[0] & q) != 0, t ^ (q - 1), t)"),
+    "bins_not_clamped": ("out[:, k] = np.minimum(v, nb - 1)", "out[:, k] = v"),
+    "targets_wrong_normalisation": ("out.append(acc * float(total) / float(n_parts))",
+                                    "out.append(acc * float(total) / float(n_parts + 1))"),
+    "split_at_bin_start": ("mid2 = (2 * before[key] + binw[key])", "mid2 = (2 * before[key])"),
+    "inclusive_prefix": ("before = np.concatenate([[0], np.cumsum(binw)[:-1]])", "before = np.cumsum(binw)"),
+    "centroid_wrong_divisor": ("cen[sel] = acc / n", "cen[sel] = acc / (n - 1)"),
+    "upsilon_over_sum": ("Ups = np.cumsum(T, axis=1) / T.mean(axis=1, keepdims=True)",
+                         "Ups = np.cumsum(T, axis=1) / T.sum(axis=1, keepdims=True)"),
+    "regression_weights_reversed": ("wk = growth ** np.arange(K)", "wk = growth ** -np.arange(K)"),
+    "regression_cut_off_by_one": ("nxt = (i - alpha) / beta", "nxt = (i - 1 - alpha) / beta"),
+}
+
+
+def _run_partition_pins(src_text, tmp_path):
+    mut = tmp_path / "partition_variant.py"
+    mut.write_text(src_text)
+    env = dict(os.environ, LESASM_PARTITION_ORACLE=str(mut))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", PART_PINS],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_partition_unmodified_copy_passes(tmp_path):
+    r = _run_partition_pins(open(PART_SRC).read(), tmp_path)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(PART_MUTANTS))
+def test_partition_pins_catch_mutant(name, tmp_path):
+    old, new = PART_MUTANTS[name]
+    src = open(PART_SRC).read()
+    assert src.count(old) >= 1, name
+    r = _run_partition_pins(src.replace(old, new), tmp_path)
+    assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
