@@ -452,6 +452,155 @@ def run_precision(args):
     mesh.close()
 
 
+def partition_bytes(mesh, nbins: int) -> dict:
+    """Algorithmic bytes of the partitioner's kernels with ideal reuse.
+    Locations: offsets (8 B per element), connectivity (4 B per element node),
+    node coordinates once (24 B per node), location and weight written (28 B
+    per element).  Split: locations read twice (bounding box, keys: 48 B),
+    weights read (4 B), keys written and read (8 B), parts written (4 B) per
+    element, plus the bins (8 B each) zeroed, scanned (read twice, written
+    once) and read by the split (twice)."""
+    E = mesh.n_elems
+    return {"centroids": 8 * (E + 1) + 4 * int(mesh.conn.size) + 24 * mesh.n_nodes + 28 * E,
+            "split": 64 * E + 8 * nbins * (1 + 3 + 2)}
+
+
+def run_partition(args):
+    """Space-filling-curve partition of the 20 M-element hybrid box (the mesh of
+    the precision workload): element locations and Gauss-point weights on the
+    GPU, then the Hilbert split into 8 parts on 128^3 bins.  A step is both
+    calls; inputs (connectivity, coordinates) resident in HBM."""
+    import torch
+    from paper_2005_05899_amd import lesasm, meshgen
+    torch.cuda.set_device(0)
+    layers = meshgen.hybrid_layers(205 * 205, 20_000_000)
+    mesh = meshgen.hybrid_box(205, 205, layers, seed=4)
+    P, level = 8, 7
+    off = torch.from_numpy(mesh.conn_offsets.astype(np.int64)).cuda()
+    conn = torch.from_numpy(mesh.conn.astype(np.int32)).cuda()
+    xyz = torch.from_numpy(mesh.coords).cuda()
+    cen, w = lesasm.element_centroids(off, conn, xyz)
+    part = lesasm.sfc_partition(cen, w, P, level=level)
+    for _ in range(args.warmup):
+        cen, w = lesasm.element_centroids(off, conn, xyz, check_input=False)
+        part = lesasm.sfc_partition(cen, w, P, level=level)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cen, w = lesasm.element_centroids(off, conn, xyz, check_input=False)
+        part = lesasm.sfc_partition(cen, w, P, level=level)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # kernel times with events on the stream the library launches on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tc, tp = [], []
+    for _ in range(args.steps):
+        ev[0].record()
+        cen, w = lesasm.element_centroids(off, conn, xyz, check_input=False)
+        ev[1].record()
+        part = lesasm.sfc_partition(cen, w, P, level=level)
+        ev[2].record()
+        ev[2].synchronize()
+        tc.append(ev[0].elapsed_time(ev[1]))
+        tp.append(ev[1].elapsed_time(ev[2]))
+    E = mesh.n_elems
+    nb = partition_bytes(mesh, 1 << (3 * level))
+    ms_c, ms_p = float(np.mean(tc)), float(np.mean(tp))
+    got = part.cpu().numpy()
+    out = {
+        "metric": "elements partitioned/s (SFC partitioner)", "value": E * args.steps / el,
+        "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 locations, int64 weights", "data": "synthetic",
+        "config": {"workload": f"hybrid box 205 x 205 cells, {E} elements, {mesh.n_nodes} nodes; "
+                               f"{P} parts, 2^{level} bins per axis, Gauss-point weights"},
+        "roofline": {"bound": "hbm", "kernel": "k_centroids", "achieved": nb["centroids"] / ms_c / 1e6,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nb["centroids"] / ms_c / 1e6 / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": nb["centroids"], "avg_ms": ms_c},
+        "split": {"ms": ms_p, "bytes": nb["split"], "GBs": nb["split"] / ms_p / 1e6},
+        "part_elements": np.bincount(got, minlength=P).tolist(),
+    }
+    if not args.no_cpu_baseline:
+        import oracle.partition as op
+        t1 = time.perf_counter()
+        rc, rw = op.element_centroids(mesh.coords, mesh.conn_offsets, mesh.conn)
+        want, _, _ = op.sfc_partition(rc, rw, P, level=level)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": E / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole {E}-element workload, one oracle run ({dt:.1f} s)"}
+        out["parity_full"] = {"parts_identical": bool(np.array_equal(got, want)),
+                              "centroids_identical": bool(np.array_equal(cen.cpu().numpy(), rc))}
+    print(json.dumps(out), flush=True)
+
+
+def run_balance(args):
+    """Correction-coefficient load balancing (Section "Load balancing") on the
+    2.0 M-element hybrid box: 8 parts from the GPU partitioner with
+    Gauss-point weights, each part assembled as a mesh of its own (its
+    interface nodes duplicated, as in the paper's substructuring) and timed;
+    the weighted regression updates the coefficients and the mesh is split
+    again.  Element-type kernels run one after another so that a part's time
+    adds up its work.  --steps assemblies are timed per part and iteration."""
+    import torch
+    from paper_2005_05899_amd import lesasm, meshgen
+    torch.cuda.set_device(0)
+    case = meshgen.hybrid_2m_case()
+    m = case.mesh
+    P, level, iters = 8, 7, 8
+    off = torch.from_numpy(m.conn_offsets.astype(np.int64)).cuda()
+    conn = torch.from_numpy(m.conn.astype(np.int32)).cuda()
+    xyz = torch.from_numpy(m.coords).cuda()
+    cen, w = lesasm.element_centroids(off, conn, xyz)
+    lam_hist, t_hist, lb, tsum, types = [], [], [], [], []
+    lam = np.ones(P)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.time()
+    for it in range(iters):
+        part = lesasm.sfc_partition(cen, w, P, lam=lam, level=level).cpu().numpy()
+        times, mix = [], []
+        for i in range(P):
+            sub, fids = meshgen.submesh(m, np.where(part == i)[0])
+            mesh = lesasm.Mesh.from_arrays(sub, case.vreman_c)
+            mesh.set_option(lesasm.OPT_CONCURRENT, 0)
+            u = mesh.to_internal(torch.from_numpy(case.u[fids]).cuda())
+            p = mesh.to_internal(torch.from_numpy(case.p[fids]).cuda())
+            rhs = torch.empty_like(u)
+            for _ in range(args.warmup):
+                mesh.assemble_momentum_rhs(u, p, case.nu, out=rhs)
+            reps = []
+            for _ in range(args.steps):
+                ev[0].record()
+                mesh.assemble_momentum_rhs(u, p, case.nu, out=rhs)
+                ev[1].record()
+                ev[1].synchronize()
+                reps.append(ev[0].elapsed_time(ev[1]))
+            times.append(float(np.median(reps)))
+            mix.append(sub.type_counts())
+            mesh.close()
+        lam_hist.append(lam.copy())
+        t_hist.append(times)
+        lb.append(float(np.mean(times) / np.max(times)))
+        tsum.append(float(np.sum(times)))
+        types.append(mix)
+        print(f"  iteration {it}: load balance {lb[-1]:.4f}, part times {np.round(times, 4).tolist()} ms "
+              f"({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
+        lam = lesasm.balance_update(lam_hist, t_hist, 1.5)
+    import oracle.partition as op
+    lam_oracle = op.balance_update(lam_hist, t_hist, 1.5)
+    out = {
+        "metric": "load balance (mean / max part assembly time, 8 parts)", "value": lb[-1], "unit": "ratio",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tsum[-1] / P,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"hybrid box 95 x 95 x 94 cells, {m.n_elems} elements, 8 parts, weighted "
+                               f"regression (weights x1.5 per iteration), {iters} iterations"},
+        "load_balance_per_iteration": lb, "sum_of_part_times_ms": tsum,
+        "lambda_per_iteration": [np.round(v, 5).tolist() for v in lam_hist],
+        "part_types_first": types[0], "part_types_last": types[-1],
+        "lambda_next_vs_oracle_max_abs": float(np.abs(lam - lam_oracle).max()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """A plain device copy of 512 MiB per step: the calibration workload for
     the hardware byte counters (FETCH_SIZE and WRITE_SIZE should read 512 MiB
@@ -486,7 +635,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["hybrid2m", "tet20m", "batch64", "precision20m", "copy"], default="hybrid2m")
+    ap.add_argument("--workload", choices=["hybrid2m", "tet20m", "batch64", "precision20m", "copy", "partition20m",
+                                           "balance8"], default="hybrid2m")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--scatter", choices=["staged", "chunk_atomic", "colour", "direct"], default="staged")
     ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatters)")
@@ -505,6 +655,10 @@ def main():
         run_precision(args)
     elif args.workload == "copy":
         run_copy(args)
+    elif args.workload == "partition20m":
+        run_partition(args)
+    elif args.workload == "balance8":
+        run_balance(args)
     else:
         run_main(args)
 

@@ -384,6 +384,74 @@ int lesasm_mesh_set_wall(lesasm_mesh *mesh, const lesasm_wall_desc *desc);
  * Errors: LESASM_E_INVALID_ARG, LESASM_E_STATE, LESASM_E_HIP. */
 int lesasm_assemble_wall(lesasm_mesh *mesh, const double *d_u, double nu, double *d_rhs, void *stream);
 
+/* ---- SFC mesh partitioning and load balancing ---------------------------- */
+/* Section "Mesh partitioning and load balancing".  The partitioner takes one
+ * location per element (the mean of its node coordinates) and optional
+ * integer weights (the paper's cost model: one unit per Gauss point), bins the
+ * locations on a regular 2^level grid over their bounding box, orders the bins
+ * along a Hilbert curve (Skilling's transposed-index construction: bits from
+ * the most significant level down, x before y before z) and cuts the weighted
+ * curve: bin b, with weight w_b and weight S_b before it on the curve, goes to
+ * the part i whose target interval [T_{i-1}, T_i) holds its midpoint
+ * S_b + w_b / 2, where T_i = (lambda_1 + ... + lambda_i) W / P (W the total
+ * weight, lambda the correction coefficients, all 1 without correction); an
+ * element takes the part of its bin.  The bin of a coordinate c on an axis
+ * with bounds [lo, hi] is floor((c - lo) / (hi - lo) 2^level), clamped to
+ * 2^level - 1 (0 on a flat axis).  Parts are contiguous along the curve; the
+ * cumulative weight of parts 0 .. i-1 is within half the largest bin weight
+ * of T_i. */
+
+/* d_centroids[n_elems][3] = mean of each element's node coordinates (nodes
+ * summed in connectivity order, then divided by their count) and
+ * d_weights[n_elems] = its Gauss points (4 nodes: 4, 5: 8, 6: 6, 8: 8).
+ * Inputs on the device: d_conn_offsets int64 [n_elems+1] (d_conn_offsets[0]
+ * = 0), d_conn int32 [conn_len] node ids, d_coords [n_nodes][3].  d_weights
+ * may be NULL.  d_status is a caller-owned device int32 that the call never
+ * clears: 1 is OR-ed into it for an element whose node count is not 4, 5, 6
+ * or 8 or whose nodes lie outside d_conn, 2 for a node id out of range; such
+ * an element's outputs are left unwritten.  Asynchronous on `stream`; read
+ * d_status after the stream has finished.
+ * Errors: LESASM_E_INVALID_ARG (NULL, negative size), LESASM_E_HIP. */
+int lesasm_element_centroids(int64_t n_elems, const int64_t *d_conn_offsets, const int32_t *d_conn, int64_t conn_len,
+                             int64_t n_nodes, const double *d_coords, double *d_centroids, int32_t *d_weights,
+                             int32_t *d_status, void *stream);
+
+/* Bytes of device workspace lesasm_sfc_partition needs for these sizes
+ * (level 1 .. 8, n_parts >= 1).  Errors: LESASM_E_INVALID_ARG. */
+int lesasm_sfc_workspace_bytes(int64_t n_elems, int n_parts, int level, size_t *bytes);
+
+/* d_part[n_elems] (int32, device) = part of every element, as described
+ * above.  d_centroids [n_elems][3] device, finite; d_weights device int32
+ * >= 0 or NULL (weight 1 each); h_lambda host [n_parts] finite, >= 0, or
+ * NULL (all 1) -- the sum should be n_parts (the last part takes what the
+ * others leave); level 1 .. 8 (8^level bins); d_work a caller-owned device
+ * buffer of at least lesasm_sfc_workspace_bytes(), 256-byte aligned.  The
+ * total weight must stay below 2^53.  Asynchronous on `stream`; the result
+ * is integer arithmetic after the binning, so it does not depend on the
+ * launch.  Errors: LESASM_E_INVALID_ARG, LESASM_E_HIP. */
+int lesasm_sfc_partition(int64_t n_elems, const double *d_centroids, const int32_t *d_weights, int n_parts,
+                         const double *h_lambda, int level, void *d_work, size_t work_bytes, int32_t *d_part,
+                         void *stream);
+
+/* Correction coefficients for the next partition from the history of
+ * iterations 0 .. n_obs-1 (host arrays, row k = iteration k):
+ * h_lambda_hist[n_obs][n_parts] the coefficients used, h_time_hist the
+ * measured time of every part.  Per splitting point i = 1 .. n_parts-1 a
+ * linear regression of the observations (Lambda_i^k, Upsilon_i^k), with
+ * Lambda_i^k = lambda_1^k + ... + lambda_i^k and Upsilon_i^k the time of the
+ * first i parts over the mean part time, weighted by growth^k (growth 1: the
+ * simple regression; 1.5: the weighted one, each newer observation weighing
+ * 50 % more), cut with y = i gives Lambda_i; lambda_out[i] = Lambda_{i+1} -
+ * Lambda_i with Lambda_0 = 0, Lambda_P = P.  With a single observation, a
+ * spread of Lambda_i below 1e-12 P, or a slope <= 0, the line through the
+ * origin and the newest observation is used instead; Lambda is clamped to be
+ * non-decreasing within [0, P].  Host only, no device work.
+ * Errors: LESASM_E_INVALID_ARG (NULL, n_parts < 1, n_obs < 1, growth <= 0,
+ * a coefficient < 0 or not finite, a time < 0 or not finite, or a zero mean
+ * time). */
+int lesasm_balance_update(int n_parts, int n_obs, const double *h_lambda_hist, const double *h_time_hist,
+                          double growth, double *h_lambda_out);
+
 /* Waits for all work queued on `stream` (a hipStream_t; NULL = the null
  * stream) and reports what the asynchronous calls could not: a failed kernel
  * or copy surfaces here as LESASM_E_HIP with the runtime's text.

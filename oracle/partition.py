@@ -32,8 +32,9 @@ y = alpha + beta x is cut with y = i, Lambda_i^{k+1} = (i - alpha) / beta;
 lambda_i^{k+1} = Lambda_i^{k+1} - Lambda_{i-1}^{k+1} with Lambda_0 = 0 and
 Lambda_P = P.  The weighted form raises each newer observation's weight by
 50 %.  Readings: a single observation gives the line through it and the
-origin; a regression with beta <= 0 or a degenerate abscissa also falls back
-to that line through the newest observation; Lambda^{k+1} is clamped to be
+origin; a regression with beta <= 0 or a degenerate abscissa (a spread of
+Lambda_i below 1e-12 P) also falls back to that line through the newest
+observation; Lambda^{k+1} is clamped to be
 non-decreasing inside [0, P].
 """
 from __future__ import annotations
@@ -168,7 +169,7 @@ def balance_update(lam_hist, t_hist, growth=1.5):
             sw = wk.sum()
             mx, my = (wk * x).sum() / sw, (wk * y).sum() / sw
             sxx = (wk * (x - mx) ** 2).sum()
-            if sxx > 0:
+            if x.max() - x.min() > 1e-12 * P and sxx > 0:
                 beta = (wk * (x - mx) * (y - my)).sum() / sxx
                 alpha = my - beta * mx
                 if beta > 0:

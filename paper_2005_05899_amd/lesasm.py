@@ -38,6 +38,7 @@ EXPORTS = [
     "lesasm_batch_rk3_eager", "lesasm_mlp_create", "lesasm_mlp_destroy", "lesasm_mlp_get_params",
     "lesasm_mlp_set_params", "lesasm_mlp_loss_grad", "lesasm_mlp_adam", "lesasm_mlp_train_step", "lesasm_mlp_commit",
     "lesasm_mlp_forward_f32", "lesasm_mlp_infer_bf16", "lesasm_mesh_set_closure", "lesasm_mesh_closure_fallbacks",
+    "lesasm_element_centroids", "lesasm_sfc_workspace_bytes", "lesasm_sfc_partition", "lesasm_balance_update",
 ]
 MLP_PARAMS = 5254
 ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
@@ -104,6 +105,9 @@ def load(path: str = LIB_PATH):
         "lesasm_mlp_adam": [P, P, ctypes.c_float, P], "lesasm_mlp_train_step": [P, P, P, I, ctypes.c_float, P, P],
         "lesasm_mlp_commit": [P], "lesasm_mlp_forward_f32": [P, P, I, P, P], "lesasm_mlp_infer_bf16": [P, P, I, P, P],
         "lesasm_mesh_set_closure": [P, P, D, D], "lesasm_mesh_closure_fallbacks": [P, P],
+        "lesasm_element_centroids": [I64, P, P, I64, I64, P, P, P, P, P],
+        "lesasm_sfc_workspace_bytes": [I64, I, I, P], "lesasm_sfc_partition": [I64, P, P, I, P, I, P, ctypes.c_size_t, P, P],
+        "lesasm_balance_update": [I, I, P, P, D, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -341,6 +345,70 @@ def divergence(mesh: Mesh, u):
 def gradient(mesh: Mesh, p):
     out = torch.empty((mesh.n_field_nodes, 3), dtype=torch.float64, device=p.device)
     check(load().lesasm_gradient(mesh._h, _ptr(p), _ptr(out), _stream()))
+    return out
+
+
+# ---- SFC partitioning and load balancing ----------------------------------
+
+def element_centroids(conn_offsets, conn, coords, weights=True, check_input=True):
+    """(centroids [n,3] f64, Gauss-point weights [n] int32 or None) of the
+    elements given by device tensors conn_offsets (int64), conn (int32) and
+    coords ([n_nodes,3] f64), computed by lesasm_element_centroids.  With
+    check_input the call waits for the stream and raises on invalid input."""
+    for t, dt in ((conn_offsets, torch.int64), (conn, torch.int32), (coords, torch.float64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("element_centroids: expects contiguous device tensors (int64, int32, float64)")
+    n = max(conn_offsets.numel() - 1, 0)
+    cen = torch.empty((n, 3), dtype=torch.float64, device=coords.device)
+    w = torch.empty(n, dtype=torch.int32, device=coords.device) if weights else None
+    status = torch.zeros(1, dtype=torch.int32, device=coords.device)
+    check(load().lesasm_element_centroids(n, _ptr(conn_offsets), _ptr(conn), conn.numel(), coords.shape[0],
+                                          _ptr(coords), _ptr(cen), None if w is None else _ptr(w), _ptr(status),
+                                          _stream()))
+    if check_input:
+        bad = int(status.item())
+        if bad:
+            raise LesasmError(-1, "element_centroids: " + ("an element has not 4, 5, 6 or 8 nodes or lies outside "
+                                                           "conn" if bad & 1 else "node id out of range"))
+    return cen, w
+
+
+def sfc_partition(centroids, weights, n_parts: int, lam=None, level: int = 7, work=None):
+    """Part (int32 device tensor) of every element: lesasm_sfc_partition on
+    device tensors centroids [n,3] f64 and weights [n] int32 (or None);
+    lam is a host sequence of n_parts correction coefficients or None."""
+    if not centroids.is_cuda or centroids.dtype != torch.float64 or not centroids.is_contiguous():
+        raise ValueError("sfc_partition: centroids must be a contiguous float64 device tensor")
+    if weights is not None and (not weights.is_cuda or weights.dtype != torch.int32 or not weights.is_contiguous()
+                                or weights.numel() != centroids.shape[0]):
+        raise ValueError("sfc_partition: weights must be a contiguous int32 device tensor, one per element")
+    n = centroids.shape[0]
+    nbytes = ctypes.c_size_t()
+    check(load().lesasm_sfc_workspace_bytes(n, int(n_parts), int(level), ctypes.byref(nbytes)))
+    if work is None or work.numel() < nbytes.value:
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=centroids.device)
+    lam_arr = None
+    if lam is not None:
+        lam_np = np.ascontiguousarray(lam, dtype=np.float64)
+        if lam_np.shape != (int(n_parts),):
+            raise ValueError("sfc_partition: lam must hold n_parts values")
+        lam_arr = lam_np.ctypes.data
+    part = torch.empty(n, dtype=torch.int32, device=centroids.device)
+    check(load().lesasm_sfc_partition(n, _ptr(centroids), None if weights is None else _ptr(weights), int(n_parts),
+                                      lam_arr, int(level), _ptr(work), work.numel(), _ptr(part), _stream()))
+    return part
+
+
+def balance_update(lam_hist, t_hist, growth: float = 1.5) -> np.ndarray:
+    """Next correction coefficients (lesasm_balance_update) from the rows of
+    coefficients used and part times measured so far."""
+    L = np.ascontiguousarray(np.atleast_2d(lam_hist), dtype=np.float64)
+    T = np.ascontiguousarray(np.atleast_2d(t_hist), dtype=np.float64)
+    if L.shape != T.shape:
+        raise ValueError("balance_update: coefficient and time histories differ in shape")
+    out = np.empty(L.shape[1], np.float64)
+    check(load().lesasm_balance_update(L.shape[1], L.shape[0], L.ctypes.data, T.ctypes.data, float(growth),
+                                       out.ctypes.data))
     return out
 
 

@@ -353,6 +353,24 @@ def _integer_modes(n_modes: int, kmax: int, rng) -> np.ndarray:
     return cand[rng.choice(len(cand), n_modes, replace=False)].astype(np.float64)
 
 
+def submesh(mesh: Mesh, elems) -> tuple[Mesh, np.ndarray]:
+    """Elements ``elems`` (parent ids, ascending) as a mesh of their own: the
+    nodes they use renumbered in ascending parent order (a node on the
+    interface with other parts appears in each of them), and, per field node
+    of the part, the parent's field node id (to slice field arrays)."""
+    elems = np.asarray(elems, np.int64)
+    off = mesh.conn_offsets
+    cnt = off[elems + 1] - off[elems]
+    new_off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    idx = np.repeat(off[elems], cnt) + (np.arange(new_off[-1]) - np.repeat(new_off[:-1], cnt))
+    nodes, inv = np.unique(mesh.conn[idx], return_inverse=True)
+    types = mesh.types[elems]
+    if mesh.field_node is None:
+        return Mesh(mesh.coords[nodes], types, new_off, inv.astype(np.int32)), nodes
+    fids, finv = np.unique(mesh.field_node[nodes], return_inverse=True)
+    return Mesh(mesh.coords[nodes], types, new_off, inv.astype(np.int32), finv.astype(np.int32), len(fids)), fids
+
+
 @dataclass
 class FourierField:
     """u(x) = sum_m a_m cos(k_m . x + phi_m) with integer wave vectors k_m."""

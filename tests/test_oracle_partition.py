@@ -228,3 +228,21 @@ def test_weighted_iteration_converges_on_a_smooth_load():
     assert lb[0] < 0.8 and lb[-1] > 0.995
     # the total time does not depend on the split
     assert np.allclose([t.sum() for t in ts], ts[0].sum(), rtol=1e-12)
+
+
+def test_parts_assembled_apart_sum_to_the_whole():
+    # substructuring: every part assembles its own elements with duplicated
+    # interface nodes; summing the parts at shared nodes gives the whole residual
+    import oracle
+    c = mg.small_hybrid_case(nx=4, ny=4, seed=3)
+    m = c.mesh
+    cen, w = P.element_centroids(m.coords, m.conn_offsets, m.conn)
+    part, _, _ = P.sfc_partition(cen, w, 5, level=3)
+    assert len(np.unique(part)) == 5
+    full = oracle.assemble(m, c.u, c.p, c.nu, c.vreman_c)
+    acc = np.zeros_like(full)
+    for i in range(5):
+        sub, fids = mg.submesh(m, np.where(part == i)[0])
+        r = oracle.assemble(sub, c.u[fids], None if c.p is None else c.p[fids], c.nu, c.vreman_c)
+        np.add.at(acc, fids, r)
+    assert np.linalg.norm(acc - full) <= 1e-13 * np.linalg.norm(full)
