@@ -377,9 +377,23 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 #pragma unroll
                 for (int m = 0; m < nm; ++m) dF[i][m] = (R)0;
         }
+        // point scalars loaded one point ahead, so that their scalar-cache
+        // latency overlaps the previous point's arithmetic
+        double qn[M::nq], wn = pt.w[0];
+#pragma unroll
+        for (int k = 0; k < M::nq; ++k) qn[k] = pt.q[0][k];
 #pragma unroll 1
         for (int g = 0; g < M::ng; ++g) {
-            const double *q = pt.q[g];
+            double qc[M::nq];
+#pragma unroll
+            for (int k = 0; k < M::nq; ++k) qc[k] = qn[k];
+            const double wc = wn;
+            if (g + 1 < M::ng) {
+#pragma unroll
+                for (int k = 0; k < M::nq; ++k) qn[k] = pt.q[g + 1][k];
+                wn = pt.w[g + 1];
+            }
+            const double *q = qc;
             R J[3][3], Gx[3][3], px[3] = {(R)0, (R)0, (R)0}, ug[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -388,7 +402,7 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
                 ug[i] = M::value(d.U[i], q, Gx[i]);
             }
             if constexpr (HAS_P) M::grad(d.P, q, px);
-            const R w = (R)pt.w[g];
+            const R w = (R)wc;
             PointFlux<R, HAS_P> o;
             point_flux<R, HAS_P, sizeof(R) == 8 && !MLP>(J, Gx, px, ug, w, nu, cd2, o);
 #pragma unroll
