@@ -41,11 +41,17 @@ WEIGHTS = os.path.join(ROOT, "paper_2005_05899_amd", "data", "closure_weights.np
 WEIGHTS_META = os.path.join(ROOT, "paper_2005_05899_amd", "data", "closure_weights.json")
 
 
-def source_hash() -> str:
-    """Hash of the kernel sources: counter summaries are valid for this hash only."""
+# Sources each kernel is built from: counter summaries are valid for these only.
+ASSEMBLY_SOURCES = ("csrc/assemble.hip", "csrc/element.hpp", "csrc/modal.hpp", "csrc/refelem.hpp", "csrc/mlp.hpp",
+                    "csrc/common.hpp", "../include/lesasm.h")
+PARTITION_SOURCES = ("csrc/partition.hip", "csrc/common.hpp", "../include/lesasm.h")
+
+
+def source_hash(files=ASSEMBLY_SOURCES) -> str:
+    """Hash of a kernel's sources: counter summaries are valid for this hash only."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2005_05899_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2005_05899_amd", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -161,14 +167,15 @@ def cpu_baseline(case, min_seconds: float = 10.0) -> dict:
                       f"({total:.1f} s), median rate"}
 
 
-def traffic_from_profiles(slot: str, workload: str = "hybrid2m"):
+def traffic_from_profiles(slot: str, workload: str = "hybrid2m", kernel: str = "k_assemble",
+                          files=ASSEMBLY_SOURCES):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_k_assemble_{slot}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{slot}_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash(files):
         return None
     return d
 
@@ -507,6 +514,7 @@ def run_partition(args):
     nb = partition_bytes(mesh, 1 << (3 * level))
     ms_c, ms_p = float(np.mean(tc)), float(np.mean(tp))
     got = part.cpu().numpy()
+    tr = traffic_from_profiles("all", "partition20m", "k_centroids", PARTITION_SOURCES)
     out = {
         "metric": "elements partitioned/s (SFC partitioner)", "value": E * args.steps / el,
         "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -516,7 +524,9 @@ def run_partition(args):
                                f"{P} parts, 2^{level} bins per axis, Gauss-point weights"},
         "roofline": {"bound": "hbm", "kernel": "k_centroids", "achieved": nb["centroids"] / ms_c / 1e6,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nb["centroids"] / ms_c / 1e6 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": nb["centroids"], "avg_ms": ms_c},
+                     "traffic": None if tr is None else tr["bytes_per_launch"],
+                     "bytes_per_launch": nb["centroids"], "avg_ms": ms_c},
+        "source_hash": source_hash(PARTITION_SOURCES),
         "split": {"ms": ms_p, "bytes": nb["split"], "GBs": nb["split"] / ms_p / 1e6},
         "part_elements": np.bincount(got, minlength=P).tolist(),
     }

@@ -35,6 +35,16 @@ int fail(int code, const std::string &msg);
                                   std::string(#expr) + ": " + hipGetErrorString(e_));             \
     } while (0)
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap so that XCD x processes a contiguous run of element blocks, which
+// keeps the nodes shared by neighbouring blocks in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, slot = b / X;
+    return x * q + (x < r ? x : r) + slot;
+}
+
 // ---- element categories ----------------------------------------------------
 // Category slot k holds type kTypes[k]; the order is also the launch order.
 constexpr int kNumCat = 4;

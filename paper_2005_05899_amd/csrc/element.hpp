@@ -22,16 +22,6 @@
 
 namespace lesasm {
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Remap so that XCD x processes a contiguous run of element blocks, which
-// keeps the nodes shared by neighbouring blocks in the same L2.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    constexpr int X = 8;
-    const int q = nb / X, r = nb % X;
-    const int x = b % X, slot = b / X;
-    return x * q + (x < r ? x : r) + slot;
-}
-
 // Element data in registers.  PYR05, PEN06 and HEX08 hold the modal
 // coefficients of coordinates, velocity and pressure (modal.hpp); the affine
 // TET04 holds node values shifted by local node 0 (in FP64, before the

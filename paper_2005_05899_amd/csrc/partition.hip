@@ -23,7 +23,7 @@ namespace lesasm {
 
 namespace {
 
-constexpr int kBboxBlocks = 512;
+constexpr int kBboxBlocks = 2048;
 constexpr int kScanTile = 4096;  // bins per scan block: 1024 threads x 4
 constexpr int kMaxLevel = 8;
 
@@ -132,13 +132,29 @@ __global__ __launch_bounds__(256) void k_bbox_partial(int64_t n, const double *_
     if (threadIdx.x < 6) partial[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_bbox_final(const double *__restrict__ partial, int nb,
-                                                   double *__restrict__ box) {
-    if (threadIdx.x >= 6) return;
-    const int d = threadIdx.x;
-    double v = d < 3 ? INFINITY : -INFINITY;
-    for (int b = 0; b < nb; ++b) v = d < 3 ? fmin(v, partial[6 * b + d]) : fmax(v, partial[6 * b + d]);
-    box[d] = v;
+__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ partial, int nb,
+                                                    double *__restrict__ box) {
+    __shared__ double sh[6][256];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], partial[6 * b + d]);
+            v[3 + d] = fmax(v[3 + d], partial[6 * b + 3 + d]);
+        }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) sh[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + w]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) box[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *__restrict__ a, int64_t n) {
@@ -147,20 +163,45 @@ __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *__restrict
 }
 
 // Hilbert key of each element's bin; bin weights summed with 64-bit atomics.
+// Neighbouring elements mostly share a bin, so each wavefront first merges
+// runs of equal keys in lane order (segmented scan over run ids) and only the
+// last lane of a run adds the run's weight: integer sums, so the bin weights
+// are exact whatever the grouping.
 __global__ __launch_bounds__(256) void k_sfc_keys(int64_t n, const double *__restrict__ c,
                                                   const int32_t *__restrict__ wts, const double *__restrict__ box,
                                                   int level, uint32_t *__restrict__ key,
                                                   unsigned long long *__restrict__ binw) {
     const int nb = 1 << level;
     const double lo0 = box[0], lo1 = box[1], lo2 = box[2], hi0 = box[3], hi1 = box[4], hi2 = box[5];
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t bx = bin_of(c[3 * e + 0], lo0, hi0, nb);
-        const uint32_t by = bin_of(c[3 * e + 1], lo1, hi1, nb);
-        const uint32_t bz = bin_of(c[3 * e + 2], lo2, hi2, nb);
-        const uint32_t h = hilbert_position(bx, by, bz, level);
-        key[e] = h;
-        const int32_t w = wts ? wts[e] : 1;
-        atomicAdd(binw + h, (unsigned long long)(long long)w);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // the loop runs the same number of times in every lane of a wavefront
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+        const int64_t e = base + threadIdx.x;
+        const bool valid = e < n;
+        uint32_t h = 0xffffffffu;
+        unsigned long long v = 0ull;
+        if (valid) {
+            const uint32_t bx = bin_of(c[3 * e + 0], lo0, hi0, nb);
+            const uint32_t by = bin_of(c[3 * e + 1], lo1, hi1, nb);
+            const uint32_t bz = bin_of(c[3 * e + 2], lo2, hi2, nb);
+            h = hilbert_position(bx, by, bz, level);
+            key[e] = h;
+            v = (unsigned long long)(long long)(wts ? wts[e] : 1);
+        }
+        const uint32_t prev = __shfl_up(h, 1);
+        const bool head = lane == 0 || prev != h;
+        const unsigned long long heads = __ballot(head);
+        const int run = __popcll(heads & (~0ull >> (63 - lane)));  // runs started at or before this lane
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long up = __shfl_up(v, o);
+            const int run_up = __shfl_up(run, o);
+            if (lane >= o && run_up == run) v += up;
+        }
+        const uint32_t next = __shfl_down(h, 1);
+        const bool tail = lane == 63 || next != h;
+        if (tail && h != 0xffffffffu) atomicAdd(binw + h, v);
     }
 }
 
@@ -329,7 +370,7 @@ extern "C" int lesasm_sfc_partition(int64_t n, const double *d_cen, const int32_
     if (h_lambda) LESASM_HIP_TRY(hipMemcpyAsync(w.lam, h_lambda, sizeof(double) * P, hipMemcpyHostToDevice, s));
     const int g = grid_for((size_t)n, 256);
     hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(256), 0, s, n, d_cen, w.partial);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, w.partial, kBboxBlocks, w.box);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, w.partial, kBboxBlocks, w.box);
     hipLaunchKernelGGL(k_zero_u64, dim3(grid_for((size_t)nbins, 256)), dim3(256), 0, s, w.cum, nbins);
     hipLaunchKernelGGL(k_sfc_keys, dim3(g), dim3(256), 0, s, n, d_cen, d_wts, w.box, level, w.key, w.cum);
     hipLaunchKernelGGL(k_scan_tile_sums, dim3(ntiles), dim3(1024), 0, s, w.cum, nbins, w.tiles);
