@@ -16,6 +16,7 @@ contractions and a full time step in both precisions) is --workload precision20m
 from __future__ import annotations
 
 import argparse
+import ctypes
 import glob
 import hashlib
 import json
@@ -31,6 +32,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MATRIX_PEAK_TFLOPS = 2500.0  # dense
+# the learned closure's network per Gauss point: 2 (10 x 64 + 64 x 64 + 64 x 6)
+MLP_FLOPS_PER_POINT = 2 * (10 * 64 + 64 * 64 + 64 * 6)
 
 # Algorithmic FP64 flops per element of the residual (per Gauss point about
 # 90 n + 175 for n nodes; the affine TET04 evaluates its geometry once):
@@ -281,9 +285,12 @@ def run_main(args):
                 mesh.precision = prec
                 lesasm.set_closure(mesh, net, meta.get("delta_ref", 0.1), 0.05)
                 el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
+                npts = sum(int((m.types == t).sum()) * GAUSS[t] for t in GAUSS)
+                mfma_tf = npts * MLP_FLOPS_PER_POINT * args.steps / el / 1e12
                 variants[f"learned_closure_{prec}"] = {
                     "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
                     "speedup_vs_fp64_vreman": elapsed / el,
+                    "network_bf16_tflops": mfma_tf, "network_frac_of_bf16_peak": mfma_tf / BF16_MATRIX_PEAK_TFLOPS,
                     "fallback_fraction": fallback_fraction(mesh, u, p, case.nu),
                     "difference_vs_fp64_vreman_oracle": field_errors(mesh.to_user(rl).cpu().numpy(), ref)}
                 lesasm.set_closure(mesh, None)
@@ -498,21 +505,26 @@ def run_partition(args):
         part = lesasm.sfc_partition(cen, w, P, level=level)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    # kernel times with events on the stream the library launches on
+    # kernel times: events on the stream the library launches on, around
+    # back-to-back calls into preallocated buffers (the queue stays full)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    tc, tp = [], []
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nbytes = ctypes.c_size_t()
+    lesasm.check(lesasm.load().lesasm_sfc_workspace_bytes(mesh.n_elems, P, level, ctypes.byref(nbytes)))
+    work = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    ev[0].record()
     for _ in range(args.steps):
-        ev[0].record()
-        cen, w = lesasm.element_centroids(off, conn, xyz, check_input=False)
-        ev[1].record()
-        part = lesasm.sfc_partition(cen, w, P, level=level)
-        ev[2].record()
-        ev[2].synchronize()
-        tc.append(ev[0].elapsed_time(ev[1]))
-        tp.append(ev[1].elapsed_time(ev[2]))
+        lesasm.element_centroids(off, conn, xyz, check_input=False, out=(cen, w, status))
+    ev[1].record()
+    for _ in range(args.steps):
+        part = lesasm.sfc_partition(cen, w, P, level=level, work=work)
+    ev[2].record()
+    ev[2].synchronize()
+    assert int(status.item()) == 0
     E = mesh.n_elems
     nb = partition_bytes(mesh, 1 << (3 * level))
-    ms_c, ms_p = float(np.mean(tc)), float(np.mean(tp))
+    ms_c, ms_p = ev[0].elapsed_time(ev[1]) / args.steps, ev[1].elapsed_time(ev[2]) / args.steps
     got = part.cpu().numpy()
     tr = traffic_from_profiles("all", "partition20m", "k_centroids", PARTITION_SOURCES)
     out = {

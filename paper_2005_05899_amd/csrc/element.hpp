@@ -501,9 +501,7 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
         // past the end repeat the last element and discard it.
         unsigned char *mlds = (unsigned char *)(lds + lds_node_doubles);
         MlpCtx mc;
-        mc.w = MlpLds{(const bf16x4_t *)mlds, (const float *)(mlds + kMlpPackedShorts * 2),
-                      (const float *)(mlds + kMlpPackedShorts * 2) + kMlpH,
-                      (const float *)(mlds + kMlpPackedShorts * 2) + 2 * kMlpH};
+        mc.w = mlp_lds_view(mlds);
         mc.scratch = mlds + kMlpLdsBytes + (threadIdx.x / 64) * kMlpWaveScratch;
         unsigned fallbacks = 0;
         const int wave0 = (threadIdx.x / 64) * 64;

@@ -193,13 +193,22 @@ static void pack_weights(const float *P, std::vector<short> &tiles, std::vector<
     for (int mt = 0; mt < 4; ++mt)  // W1^T: rows = hidden, k = input
         for (int i = 0; i < 16; ++i)
             for (int k = 0; k < 16; ++k) put(mt, i, k, k < kMlpIn ? P[OFF_W1 + k * kMlpH + 16 * mt + i] : 0.f);
-    for (int mt = 0; mt < 4; ++mt)  // W2^T tiles (mt, ks)
-        for (int ks = 0; ks < 4; ++ks)
+    // W2^T tiles (mt, kb) of K = 32: A[i][k] in lane i + 16 (k/8), slot k%8;
+    // K index k of block kb is hidden unit 16 (2 kb + s/4) + 4 (k/8) + s%4, s = k%8
+    for (int mt = 0; mt < 4; ++mt)
+        for (int kb = 0; kb < 2; ++kb)
             for (int i = 0; i < 16; ++i)
-                for (int k = 0; k < 16; ++k) put(4 + 4 * mt + ks, i, k, P[OFF_W2 + (16 * ks + k) * kMlpH + 16 * mt + i]);
+                for (int k = 0; k < 32; ++k) {
+                    const int q = k / 8, s = k % 8;
+                    const int unit = 16 * (2 * kb + s / 4) + 4 * q + s % 4;
+                    const int lane = i + 16 * q;
+                    tiles[kMlpW2Shorts + ((size_t)(2 * mt + kb) * 64 + lane) * 8 + s] =
+                        bf(P[OFF_W2 + unit * kMlpH + 16 * mt + i]);
+                }
     for (int ks = 0; ks < 4; ++ks)  // W3^T: rows = outputs (6 used)
         for (int i = 0; i < 16; ++i)
-            for (int k = 0; k < 16; ++k) put(20 + ks, i, k, i < kMlpOut ? P[OFF_W3 + (16 * ks + k) * kMlpOut + i] : 0.f);
+            for (int k = 0; k < 16; ++k)
+                put(kMlpW3Tile + ks, i, k, i < kMlpOut ? P[OFF_W3 + (16 * ks + k) * kMlpOut + i] : 0.f);
     bias.assign(kMlpH + kMlpH + 8, 0.f);
     for (int j = 0; j < kMlpH; ++j) {
         bias[j] = P[OFF_B1 + j];

@@ -7,8 +7,15 @@
 //   v_mfma_f32_16x16x16_bf16:  A[i][k] in lane i + 16 (k/4), slot k%4
 //                              B[k][j] in lane j + 16 (k/4), slot k%4
 //                              D[i][j] in lane j + 16 (i/4), slot i%4
+// Layer 2 uses gfx950's v_mfma_f32_16x16x32_bf16 (K = 32 per instruction:
+// A[i][k] in lane i + 16 (k/8), slot k%8, B likewise), with its 32 K values
+// taken from two row tiles t0, t1 of H1: slot s of lane j + 16 q holds hidden
+// unit 16 t0 + 4 q + s (s < 4) or 16 t1 + 4 q + s - 4, which is exactly what
+// that lane holds of the two tiles, so H1 needs no movement between lanes; the
+// W2 tiles are packed with the same numbering of the hidden units.
 // Weights are packed once into those A tiles (W1^T: 4 row tiles, K padded
-// from 10 to 16; W2^T: 4 x 4 tiles; W3^T: 1 row tile, 6 of 16 rows used).
+// from 10 to 16; W2^T: 4 x 2 tiles of K = 32; W3^T: 1 row tile, 6 of 16 rows
+// used, 4 K tiles).
 // Inputs:  x = [G / |G|_F (9), log(Delta / Delta_ref)], outputs 6 symmetric
 // components (xx, yy, zz, xy, xz, yz) before the trace removal.
 #pragma once
@@ -22,9 +29,12 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpIn = 10, kMlpH = 64, kMlpOut = 6;
 constexpr int kMlpParams = kMlpIn * kMlpH + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH * kMlpOut + kMlpOut;  // 5254
-// packed A tiles: 4 (W1) + 16 (W2) + 4 (W3), each 64 lanes x 4 bf16
+// packed A tiles: 4 (W1, 64 lanes x 4 bf16), 8 (W2, 64 lanes x 8 bf16), 4 (W3,
+// 64 lanes x 4 bf16); in units of 64 lanes x 4 bf16: 4 + 16 + 4
 constexpr int kMlpTiles = 4 + 16 + 4;
 constexpr int kMlpPackedShorts = kMlpTiles * 64 * 4;
+constexpr int kMlpW2Shorts = 4 * 64 * 4;   // offset of the W2 tiles
+constexpr int kMlpW3Tile = 20;              // first W3 tile, in 64 x 4 units
 // LDS bytes of the packed weights and biases (b1, b2, b3 padded to 8)
 constexpr int kMlpLdsBytes = kMlpPackedShorts * 2 + (kMlpH + kMlpH + 8) * 4;
 // per-wavefront LDS scratch: 64 samples x 16 bf16 inputs, then 64 x 8 floats outputs
@@ -37,10 +47,20 @@ __device__ __forceinline__ short f2bf(float f) {
     return (short)(u >> 16);
 }
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
 struct MlpLds {
-    const bf16x4_t *tiles;  // [kMlpTiles][64]
+    const bf16x4_t *tiles;  // W1 and W3 tiles, [tile][64] in 64 x 4 units
+    const bf16x8_t *w2;     // W2 tiles, [2 mt + kb][64]
     const float *b1, *b2, *b3;
 };
+
+// View of packed weights already staged in LDS at `lds`.
+__device__ __forceinline__ MlpLds mlp_lds_view(const unsigned char *lds) {
+    const short *t = (const short *)lds;
+    const float *b = (const float *)(lds + kMlpPackedShorts * 2);
+    return MlpLds{(const bf16x4_t *)t, (const bf16x8_t *)(t + kMlpW2Shorts), b, b + kMlpH, b + 2 * kMlpH};
+}
 
 // Copy packed weights (global, bf16 tiles + f32 biases) into LDS; call with the
 // whole workgroup, followed by a barrier.
@@ -51,7 +71,7 @@ __device__ __forceinline__ MlpLds mlp_stage(const short *__restrict__ packed, co
         ((bf16x4_t *)t)[k] = ((const bf16x4_t *)packed)[k];
     float *b = (float *)(lds + kMlpPackedShorts * 2);
     for (int k = threadIdx.x; k < kMlpH + kMlpH + 8; k += blockDim.x) b[k] = bias[k];
-    return MlpLds{(const bf16x4_t *)t, b, b + kMlpH, b + 2 * kMlpH};
+    return mlp_lds_view(lds);
 }
 
 // Two floats to two bf16 (round to nearest even, the hardware conversion),
@@ -68,8 +88,18 @@ __device__ __forceinline__ bf16x4_t pack_bf16x4(float a, float b, float c, float
     const u32x2_t v = {lo, hi};
     return __builtin_bit_cast(bf16x4_t, v);
 }
-// max(v, 0) as one median-of-three instruction (finite inputs)
-__device__ __forceinline__ float relu(float v) { return __builtin_amdgcn_fmed3f(v, 0.f, 3.0e38f); }
+// max(v, 0) on four bf16 values: a negative bf16 is a negative 16-bit
+// integer, so two packed integer maxima clear the negative values; rounding
+// then rectifying equals rectifying then rounding.
+__device__ __forceinline__ bf16x4_t relu_bf16x4(bf16x4_t v) {
+    return __builtin_elementwise_max(v, bf16x4_t{0, 0, 0, 0});
+}
+// Two bf16x4 register quads as one bf16x8 operand (slots 0-3, then 4-7).
+__device__ __forceinline__ bf16x8_t cat_bf16x8(bf16x4_t lo, bf16x4_t hi) {
+    typedef short s16x8_t __attribute__((ext_vector_type(8)));
+    const s16x8_t v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(bf16x8_t, v);
+}
 
 // Whole-wavefront evaluation: every lane supplies the 10 inputs of its own
 // sample and receives its 6 outputs.  All 64 lanes must call it together
@@ -110,7 +140,7 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bx[nt], b, 0, 0, 0);
-            h1[mt][nt] = pack_bf16x4(relu(acc[0]), relu(acc[1]), relu(acc[2]), relu(acc[3]));
+            h1[mt][nt] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
         }
     }
     // layers 2 and 3 by row tile of H2: H2^T = relu(W2^T H1^T + b2), Y^T += W3^T H2^T
@@ -127,16 +157,17 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[nt] = b;
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const bf16x4_t a = w.tiles[(4 + 4 * mt + ks) * 64 + lane];
+        for (int kb = 0; kb < 2; ++kb) {
+            const bf16x8_t a = w.w2[(2 * mt + kb) * 64 + lane];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[ks][nt], acc[nt], 0, 0, 0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, cat_bf16x8(h1[2 * kb][nt], h1[2 * kb + 1][nt]),
+                                                                  acc[nt], 0, 0, 0);
         }
-        const bf16x4_t a3 = w.tiles[(20 + mt) * 64 + lane];
+        const bf16x4_t a3 = w.tiles[(kMlpW3Tile + mt) * 64 + lane];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const bf16x4_t h2 = pack_bf16x4(relu(acc[nt][0]), relu(acc[nt][1]), relu(acc[nt][2]), relu(acc[nt][3]));
+            const bf16x4_t h2 = relu_bf16x4(pack_bf16x4(acc[nt][0], acc[nt][1], acc[nt][2], acc[nt][3]));
             acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, h2, acc3[nt], 0, 0, 0);
         }
     }

@@ -350,18 +350,26 @@ def gradient(mesh: Mesh, p):
 
 # ---- SFC partitioning and load balancing ----------------------------------
 
-def element_centroids(conn_offsets, conn, coords, weights=True, check_input=True):
+def element_centroids(conn_offsets, conn, coords, weights=True, check_input=True, out=None):
     """(centroids [n,3] f64, Gauss-point weights [n] int32 or None) of the
     elements given by device tensors conn_offsets (int64), conn (int32) and
     coords ([n_nodes,3] f64), computed by lesasm_element_centroids.  With
-    check_input the call waits for the stream and raises on invalid input."""
+    check_input the call waits for the stream and raises on invalid input.
+    out = (centroids, weights or None, status int32 [1], zeroed by the caller)
+    reuses buffers."""
     for t, dt in ((conn_offsets, torch.int64), (conn, torch.int32), (coords, torch.float64)):
         if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise ValueError("element_centroids: expects contiguous device tensors (int64, int32, float64)")
     n = max(conn_offsets.numel() - 1, 0)
-    cen = torch.empty((n, 3), dtype=torch.float64, device=coords.device)
-    w = torch.empty(n, dtype=torch.int32, device=coords.device) if weights else None
-    status = torch.zeros(1, dtype=torch.int32, device=coords.device)
+    if out is not None:
+        cen, w, status = out
+        if cen.shape != (n, 3) or cen.dtype != torch.float64 or (w is not None and w.shape != (n,)) \
+                or status.dtype != torch.int32:
+            raise ValueError("element_centroids: output buffers of the wrong shape or type")
+    else:
+        cen = torch.empty((n, 3), dtype=torch.float64, device=coords.device)
+        w = torch.empty(n, dtype=torch.int32, device=coords.device) if weights else None
+        status = torch.zeros(1, dtype=torch.int32, device=coords.device)
     check(load().lesasm_element_centroids(n, _ptr(conn_offsets), _ptr(conn), conn.numel(), coords.shape[0],
                                           _ptr(coords), _ptr(cen), None if w is None else _ptr(w), _ptr(status),
                                           _stream()))
