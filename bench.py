@@ -427,11 +427,30 @@ def run_precision(args):
                       "u": uu, "p": pp}
         st.close()
         print(f"  step {prec}: {step[prec]['ms']:.1f} ms, {it} CG iterations", file=sys.stderr, flush=True)
+    # the pressure CG alone: a fixed number of iterations on this mesh's Laplacian
+    st = lesasm.Stepper(mesh, case.nu, dt, rtol=1e-30, maxit=300)
+    b = lesasm.divergence(mesh, u)
+    st.pressure_solve(b)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    st.pressure_solve(b)
+    torch.cuda.synchronize()
+    el_cg = time.perf_counter() - ts
+    it_cg, _ = st.stats()
+    nnz = ctypes.c_int64()
+    lesasm.check(lesasm.load().lesasm_stepper_laplacian(st._h, None, None, None, ctypes.byref(nnz)))
+    n_rows = m.n_field_nodes
+    cg_bytes = cg_bytes_per_iteration(nnz.value, n_rows)
+    ms_it = 1e3 * el_cg / it_cg
+    step["pressure_cg"] = {"iterations": it_cg, "ms_per_iteration": ms_it, "rows": n_rows, "nonzeros": nnz.value,
+                           "algorithmic_bytes_per_iteration": cg_bytes,
+                           "achieved_GBs": cg_bytes / ms_it / 1e6, "frac_of_hbm": cg_bytes / ms_it / 1e6 / HBM_PEAK_GBS}
+    st.close()
     du64 = mesh.to_user(step["fp64"]["u"] - u).cpu().numpy()
     du32 = mesh.to_user(step["fp32"]["u"] - u).cpu().numpy()
     u64 = mesh.to_user(step["fp64"]["u"]).cpu().numpy()
     u32 = mesh.to_user(step["fp32"]["u"]).cpu().numpy()
-    for prec in step:
+    for prec in ("fp64", "fp32"):
         del step[prec]["u"], step[prec]["p"]
     step_cmp = {"velocity_fp32_vs_fp64": field_errors(u32, u64),
                 "increment_fp32_vs_fp64": field_errors(du32, du64), "dt": dt}
@@ -464,6 +483,14 @@ def run_precision(args):
     }
     print(json.dumps(out), flush=True)
     mesh.close()
+
+
+def cg_bytes_per_iteration(nnz: int, n: int) -> int:
+    """Algorithmic bytes of one Jacobi-CG iteration: the SpMV reads 12 B per
+    nonzero (value, column), 4 B per row pointer and p once, writes q; the
+    update reads x, p, r, q and the diagonal and writes x, r, z; the direction
+    reads z, p and writes p (8 B per row each)."""
+    return 12 * nnz + 4 * (n + 1) + 8 * n * (2 + 8 + 3)
 
 
 def partition_bytes(mesh, nbins: int) -> dict:
