@@ -219,10 +219,11 @@ def run_main(args):
                                "algorithmic_tflops": fl / (avg * 1e-3) / 1e12,
                                "frac_of_peak": fl / (avg * 1e-3) / 1e12 / peak,
                                "algorithmic_GBs": per_type_bytes(m, t) / (avg * 1e-3) / 1e9}
-        for extra in ("gather", "fill"):
+        n_asm = max(kt[slot][1] for slot in SLOT.values())
+        for extra in ("gather", "fill"):  # per assembly (the gather is one launch per node class)
             ms, n = kt[extra]
             if n:
-                table[extra] = {"avg_ms": ms / n, "launches": n}
+                table[extra] = {"avg_ms": ms / n_asm, "launches": n}
         return table
 
     per_kernel = kernel_table(kt)
