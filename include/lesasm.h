@@ -426,9 +426,11 @@ int lesasm_sfc_workspace_bytes(int64_t n_elems, int n_parts, int level, size_t *
  * NULL (all 1) -- the sum should be n_parts (the last part takes what the
  * others leave); level 1 .. 8 (8^level bins); d_work a caller-owned device
  * buffer of at least lesasm_sfc_workspace_bytes(), 256-byte aligned.  The
- * total weight must stay below 2^53.  Asynchronous on `stream`; the result
- * is integer arithmetic after the binning, so it does not depend on the
- * launch.  Errors: LESASM_E_INVALID_ARG, LESASM_E_HIP. */
+ * total weight must stay below 2^53.  Asynchronous on `stream` (h_lambda is
+ * read before the call returns: up to 256 coefficients travel with the
+ * launch; with more, the call copies them and waits for the stream); the
+ * result is integer arithmetic after the binning, so it does not depend on
+ * the launch.  Errors: LESASM_E_INVALID_ARG, LESASM_E_HIP. */
 int lesasm_sfc_partition(int64_t n_elems, const double *d_centroids, const int32_t *d_weights, int n_parts,
                          const double *h_lambda, int level, void *d_work, size_t work_bytes, int32_t *d_part,
                          void *stream);

@@ -260,15 +260,22 @@ __global__ __launch_bounds__(1024) void k_scan_apply(unsigned long long *__restr
     }
 }
 
+// Correction coefficients passed by value (up to kArgLambda parts).
+constexpr int kArgLambda = 256;
+struct LambdaArg {
+    double v[kArgLambda];
+};
+
 // t2[i] = 2 T_{i+1} = 2 (Lambda_{i+1} W / P), i < P - 1 (one thread: the
-// coefficients are summed in order).
-__global__ void k_targets(const double *__restrict__ lam, int P, const unsigned long long *__restrict__ cum,
-                          int64_t nbins, double *__restrict__ t2) {
+// coefficients are summed in order).  Coefficients from `lam` (device) if set,
+// else from `la` if use_arg, else all 1.
+__global__ void k_targets(const double *__restrict__ lam, LambdaArg la, int use_arg, int P,
+                          const unsigned long long *__restrict__ cum, int64_t nbins, double *__restrict__ t2) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double W = (double)cum[nbins - 1];
     double acc = 0.0;
     for (int i = 0; i + 1 < P; ++i) {
-        acc = acc + (lam ? lam[i] : 1.0);
+        acc = acc + (lam ? lam[i] : use_arg ? la.v[i] : 1.0);
         t2[i] = 2.0 * (acc * W / (double)P);
     }
 }
@@ -367,7 +374,16 @@ extern "C" int lesasm_sfc_partition(int64_t n, const double *d_cen, const int32_
     hipStream_t s = (hipStream_t)stream;
     const int64_t nbins = (int64_t)1 << (3 * level);
     const int ntiles = (int)((nbins + kScanTile - 1) / kScanTile);
-    if (h_lambda) LESASM_HIP_TRY(hipMemcpyAsync(w.lam, h_lambda, sizeof(double) * P, hipMemcpyHostToDevice, s));
+    // up to kArgLambda coefficients travel in the kernel arguments; more are
+    // copied and waited for, so h_lambda is never read after the call returns
+    LambdaArg la{};
+    const bool by_arg = h_lambda && P <= kArgLambda;
+    if (by_arg)
+        for (int i = 0; i < P; ++i) la.v[i] = h_lambda[i];
+    if (h_lambda && !by_arg) {
+        LESASM_HIP_TRY(hipMemcpyAsync(w.lam, h_lambda, sizeof(double) * P, hipMemcpyHostToDevice, s));
+        LESASM_HIP_TRY(hipStreamSynchronize(s));
+    }
     const int g = grid_for((size_t)n, 256);
     hipLaunchKernelGGL(k_bbox_partial, dim3(kBboxBlocks), dim3(256), 0, s, n, d_cen, w.partial);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, w.partial, kBboxBlocks, w.box);
@@ -376,7 +392,8 @@ extern "C" int lesasm_sfc_partition(int64_t n, const double *d_cen, const int32_
     hipLaunchKernelGGL(k_scan_tile_sums, dim3(ntiles), dim3(1024), 0, s, w.cum, nbins, w.tiles);
     hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(1024), 0, s, w.tiles, ntiles);
     hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(1024), 0, s, w.cum, nbins, w.tiles);
-    hipLaunchKernelGGL(k_targets, dim3(1), dim3(1), 0, s, h_lambda ? w.lam : nullptr, P, w.cum, nbins, w.t2);
+    hipLaunchKernelGGL(k_targets, dim3(1), dim3(1), 0, s, (h_lambda && !by_arg) ? w.lam : nullptr, la, by_arg ? 1 : 0,
+                       P, w.cum, nbins, w.t2);
     hipLaunchKernelGGL(k_assign, dim3(g), dim3(256), 0, s, n, w.key, w.cum, w.t2, P, d_part);
     LESASM_HIP_TRY(hipGetLastError());
     return LESASM_OK;
