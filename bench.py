@@ -123,6 +123,30 @@ def time_assembly(torch, mesh, u, p, nu, steps, warmup, concurrent=True):
     return elapsed, kt, rhs
 
 
+def time_graph_replay(torch, mesh, u, p, nu, steps, warmup) -> float:
+    """Seconds for `steps` replays of one assembly captured in a HIP graph
+    (the same launches: fork to the side streams, element kernels, join,
+    gather), on a stream of its own."""
+    s = torch.cuda.Stream()
+    rhs = torch.empty_like(u)
+    with torch.cuda.stream(s):
+        mesh.assemble_momentum_rhs(u, p, nu, out=rhs)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        mesh.assemble_momentum_rhs(u, p, nu, out=rhs)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    del g
+    return el
+
+
 def time_wall(torch, mesh, m, case, u, steps) -> dict:
     """The boundary assembly of the wall model (wall z = 0): time per call and
     error against the oracle."""
@@ -206,6 +230,7 @@ def run_main(args):
                                           concurrent=not args.isolated)
     # the same launches one kernel at a time: isolated durations for the roofline
     el_iso, kt, _ = time_assembly(torch, mesh, u, p, case.nu, args.steps, 2, concurrent=False)
+    el_graph = time_graph_replay(torch, mesh, u, p, case.nu, args.steps, args.warmup)
     E = m.n_elems
     value = E * args.steps / elapsed
     peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
@@ -267,6 +292,8 @@ def run_main(args):
         "kernels_isolated": per_kernel,
         "kernels_concurrent": per_kernel_conc,
         "isolated_ms_per_step": 1e3 * el_iso / args.steps,
+        "graph_replay": {"value": E * args.steps / el_graph, "ms_per_step": 1e3 * el_graph / args.steps,
+                         "note": "the same assembly captured once in a HIP graph and replayed"},
         "source_hash": source_hash(),
     }
     if args.variants:
@@ -685,8 +712,8 @@ def run_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100, help="untimed steps first (lets the clocks settle)")
     ap.add_argument("--workload", choices=["hybrid2m", "tet20m", "batch64", "precision20m", "copy", "partition20m",
                                            "balance8"], default="hybrid2m")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")

@@ -325,3 +325,39 @@ def test_hybrid_2m_other_scatters(torch_cuda, hybrid2m, scatter):
     got, m = run_gpu(torch_cuda, c, scatter=scatter)
     assert_close(got, ref, TOL64, f"2M hybrid fp64 {scatter}")
     m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_captured_assembly_replays(torch_cuda, small, precision):
+    # one assembly (fork to the side streams, four element kernels, join,
+    # gather) captured in a HIP graph; every replay, with eager work in
+    # between, must equal the eager result and match the oracle
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    c, ref = small
+    m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+    m.precision = precision
+    u = m.to_internal(torch.from_numpy(c.u).cuda())
+    p = m.to_internal(torch.from_numpy(c.p).cuda())
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        eager = m.assemble_momentum_rhs(u, p, c.nu).clone()
+        out = torch.empty_like(u)
+        m.assemble_momentum_rhs(u, p, c.nu, out=out)  # warm the stream
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        m.assemble_momentum_rhs(u, p, c.nu, out=out)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        out.fill_(float("nan"))
+        other = m.assemble_momentum_rhs(u * 0.5, p, c.nu)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        diff = float((out - eager).abs().max() / eager.abs().max())
+        assert diff <= (1e-14 if precision == "fp64" else 1e-6), (rep, diff)
+        assert torch.isfinite(other).all()
+    assert_close(m.to_user(out).cpu().numpy(), ref, TOL64 if precision == "fp64" else TOL32, f"graph {precision}")
+    del g
+    m.close()
