@@ -46,7 +46,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // ---- element categories ----------------------------------------------------
-// Category slot k holds type kTypes[k]; the order is also the launch order.
+// Category slot k holds type kTypes[k] (the chunked path launches them in its own order).
 constexpr int kNumCat = 4;
 constexpr int kTypes[kNumCat] = {LESASM_TET04, LESASM_PYR05, LESASM_PEN06, LESASM_HEX08};
 
