@@ -54,10 +54,15 @@ PARTITION_SOURCES = ("csrc/partition.hip", "csrc/common.hpp")
 
 
 def source_hash(files=ASSEMBLY_SOURCES) -> str:
-    """Hash of a kernel's sources: counter summaries are valid for this hash only."""
+    """Hash of a kernel's code (comments and whitespace removed): counter
+    summaries are valid for this hash only."""
+    import re
     h = hashlib.sha256()
     for f in files:
-        h.update(open(os.path.join(ROOT, "paper_2005_05899_amd", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2005_05899_amd", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
