@@ -274,6 +274,16 @@ int lesasm_batch_destroy(lesasm_batch *batch);
 int lesasm_batch_configure(lesasm_batch *batch, int chunk, int order, int grid_per_cu);
 int lesasm_batch_get_config(const lesasm_batch *batch, int *chunk, int *order, int *grid_per_cu, int *n_items);
 
+/* Kernel layout of the batch: 0 (default) one persistent kernel drains the
+ * whole queue, switching on the element type of each item; 1 the queue is
+ * ordered type by type (the chosen order kept inside each type) and four
+ * persistent kernels, one per element type (each compiled, and resident, for
+ * its own type), drain their parts concurrently on forked streams.  Rebuilds
+ * the queue (synchronises).  Errors: LESASM_E_INVALID_ARG, LESASM_E_UNSUPPORTED
+ * (a value other than 0 or 1). */
+int lesasm_batch_set_per_type(lesasm_batch *batch, int per_type);
+int lesasm_batch_get_per_type(const lesasm_batch *batch, int *per_type);
+
 /* Residual assembly of every mesh: host arrays of n device pointers
  * d_u[i] ([n_field_nodes_i][3]), d_p[i] (or d_p == NULL for none), nu[i],
  * d_rhs[i] (overwritten).  Same semantics as lesasm_assemble_momentum_rhs per
@@ -284,9 +294,10 @@ int lesasm_batch_assemble(lesasm_batch *batch, const double *const *d_u, const d
                           const double *nu, double *const *d_rhs, void *stream);
 
 /* Autotuner: times the batched assembly for chunk lengths {128, 256, 512,
- * 1024} x the three queue orders x {2, 4} workgroups per compute unit
- * (median of `reps` runs after one warm-up) and keeps the fastest.  With a
- * cache_path, a line "signature chunk order grid ms" is looked up first
+ * 1024} x the three queue orders x {2, 4} workgroups per compute unit x the
+ * two kernel layouts (median of `reps` runs after one warm-up) and keeps the
+ * fastest.  With a cache_path, a line "signature chunk order grid per_type
+ * ms" is looked up first
  * (signature = compute units and element counts per mesh and type) and
  * appended after tuning.  *best_ms receives the time.  Synchronises. */
 int lesasm_batch_tune(lesasm_batch *batch, const double *const *d_u, const double *const *d_p, const double *nu,

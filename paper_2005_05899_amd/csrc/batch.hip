@@ -46,10 +46,12 @@ struct BatchMeshDev {
     const double *stage, *mass;
 };
 
+constexpr int kHeads = 1 + kNumCat;  // the mixed queue's counter, then one per type
+
 __global__ void k_batch_begin(BatchCall args, BatchCall *dst, int *head) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *dst = args;
-        *head = 0;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *dst = args;
+        if (threadIdx.x < kHeads) head[threadIdx.x] = 0;
     }
 }
 
@@ -84,6 +86,30 @@ __global__ __launch_bounds__(256) void k_batch_assemble(const BatchEntry *__rest
         __syncthreads();
         if (w >= nwork) return;
         batch_item<R, HAS_P>(entries[wentry[w]], call, wchunk[w], lds);
+        __syncthreads();
+    }
+}
+
+// Per-type persistent kernel: the same queue walk over the items of one
+// element type only, so each type is compiled (and occupies registers) on
+// its own and the four run concurrently.
+template <int T, typename R, bool HAS_P>
+__global__ __launch_bounds__(256) void k_batch_assemble_type(const BatchEntry *__restrict__ entries,
+                                                             const BatchCall *__restrict__ call,
+                                                             const int32_t *__restrict__ wentry,
+                                                             const int32_t *__restrict__ wchunk, int nwork, int *head) {
+    extern __shared__ __align__(16) double lds[];
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = atomicAdd(head, 1);
+        __syncthreads();
+        const int w = item;
+        __syncthreads();
+        if (w >= nwork) return;
+        const BatchEntry &be = entries[wentry[w]];
+        const int mi = be.mesh;
+        chunk_body<T, R, HAS_P, false, true>(be.v, wchunk[w], lds, be.xyz, call->u[mi], HAS_P ? call->p[mi] : nullptr,
+                                             call->nu[mi], be.cv, call->rhs[mi]);
         __syncthreads();
     }
 }
@@ -165,6 +191,13 @@ struct lesasm_batch {
     int32_t *d_wentry = nullptr, *d_wchunk = nullptr;
     int *d_head = nullptr;
     int nwork = 0, lds_doubles = 0;
+    // per-type mode: the queue is type-major, type category k holds items
+    // [type_off[k], type_off[k+1]) and needs type_lds[k] doubles of LDS
+    int per_type = 0;
+    int type_off[kNumCat + 1] = {0};
+    int type_lds[kNumCat] = {0};
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     int64_t total_gather = 0, total_nodes = 0;
     std::vector<void *> allocs;
     // Runge-Kutta work arrays (one slab each, per-mesh offsets) and the graph
@@ -209,6 +242,11 @@ void batch_free(lesasm_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (int i = 0; i < 3; ++i) {
+        if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
+        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    }
     for (void *p : b->allocs) (void)hipFree(p);
     delete b;
 }
@@ -220,11 +258,12 @@ int build_work(lesasm_batch *b) {
     struct Item {
         int32_t entry, chunk;
         int64_t cost;
-        int mesh;
+        int mesh, cat;
     };
     std::vector<Item> items;
     std::vector<BatchEntry> entries;
     int lds = 0;
+    for (int k = 0; k < kNumCat; ++k) b->type_lds[k] = 0;
     for (size_t mi = 0; mi < b->meshes.size(); ++mi) {
         lesasm_mesh *m = b->meshes[mi];
         for (int k = 0; k < kNumCat; ++k) {
@@ -243,8 +282,9 @@ int build_work(lesasm_batch *b) {
             be.mesh = (int)mi;
             entries.push_back(be);
             lds = std::max(lds, c.lds_doubles);
+            b->type_lds[k] = std::max(b->type_lds[k], c.lds_doubles);
             for (int j = 0; j < c.n_chunks; ++j)
-                items.push_back({eid, j, (int64_t)(eoff[j + 1] - eoff[j]) * ng, (int)mi});
+                items.push_back({eid, j, (int64_t)(eoff[j + 1] - eoff[j]) * ng, (int)mi, k});
         }
     }
     if (b->order == LESASM_ORDER_LARGEST_FIRST) {
@@ -264,6 +304,12 @@ int build_work(lesasm_batch *b) {
             if (!any) break;
         }
     }
+    // per-type mode: the same order inside each type, types one after another
+    if (b->per_type)
+        std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cat < y.cat; });
+    for (int k = 0; k <= kNumCat; ++k) b->type_off[k] = 0;
+    for (const Item &it : items) b->type_off[it.cat + 1]++;
+    for (int k = 0; k < kNumCat; ++k) b->type_off[k + 1] += b->type_off[k];
     std::vector<int32_t> we(items.size()), wc(items.size());
     for (size_t i = 0; i < items.size(); ++i) {
         we[i] = items[i].entry;
@@ -315,6 +361,7 @@ int build_tables(lesasm_batch *b) {
 
 int rebuild(lesasm_batch *b) {
     for (lesasm_mesh *m : b->meshes) {
+        if (m->chunk_elems == b->chunk) continue;  // chunks already of this length
         int st = lesasm_mesh_set_option(m, LESASM_OPT_CHUNK, b->chunk);
         if (st) return st;
     }
@@ -331,11 +378,54 @@ int rebuild(lesasm_batch *b) {
 }
 
 // Launch of the whole batch assembly (begin, persistent kernel, gather) on s.
+template <int T>
+void launch_type(lesasm_batch *b, int k, bool has_p, bool fp32, hipStream_t s) {
+    const int n = b->type_off[k + 1] - b->type_off[k];
+    if (n <= 0) return;
+    const int grid = std::max(1, std::min(n, b->n_cu * b->grid_per_cu));
+    const size_t shm = sizeof(double) * (size_t)b->type_lds[k];
+    const int32_t *we = b->d_wentry + b->type_off[k], *wc = b->d_wchunk + b->type_off[k];
+    int *head = b->d_head + 1 + k;
+    if (fp32) {
+        if (has_p) hipLaunchKernelGGL((k_batch_assemble_type<T, float, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
+        else hipLaunchKernelGGL((k_batch_assemble_type<T, float, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
+    } else {
+        if (has_p) hipLaunchKernelGGL((k_batch_assemble_type<T, double, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
+        else hipLaunchKernelGGL((k_batch_assemble_type<T, double, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
+    }
+}
+
 int batch_launch(lesasm_batch *b, const BatchCall &call, bool has_p, bool fp32, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, call, b->d_call, b->d_head);
     const int grid = std::max(1, std::min(b->nwork, b->n_cu * b->grid_per_cu));
     const size_t shm = sizeof(double) * (size_t)b->lds_doubles;
-    if (b->nwork > 0) {
+    if (b->per_type && b->nwork > 0) {
+        // the four type kernels on forked streams (order as the single-mesh
+        // path: HEX08, TET04, PYR05, PEN06), joined before the gather
+        LESASM_HIP_TRY(hipEventRecord(b->ev_fork, s));
+        static constexpr int kOrder[kNumCat] = {3, 0, 1, 2};
+        int used = 0;
+        for (int kk = 0; kk < kNumCat; ++kk) {
+            const int k = kOrder[kk];
+            if (b->type_off[k + 1] == b->type_off[k]) continue;
+            hipStream_t sk = s;
+            if (used > 0) {
+                sk = b->side[used - 1];
+                LESASM_HIP_TRY(hipStreamWaitEvent(sk, b->ev_fork, 0));
+            }
+            ++used;
+            switch (kTypes[k]) {
+            case LESASM_TET04: launch_type<LESASM_TET04>(b, k, has_p, fp32, sk); break;
+            case LESASM_PYR05: launch_type<LESASM_PYR05>(b, k, has_p, fp32, sk); break;
+            case LESASM_PEN06: launch_type<LESASM_PEN06>(b, k, has_p, fp32, sk); break;
+            case LESASM_HEX08: launch_type<LESASM_HEX08>(b, k, has_p, fp32, sk); break;
+            }
+        }
+        for (int i = 0; i + 1 < used; ++i) {
+            LESASM_HIP_TRY(hipEventRecord(b->ev_join[i], b->side[i]));
+            LESASM_HIP_TRY(hipStreamWaitEvent(s, b->ev_join[i], 0));
+        }
+    } else if (b->nwork > 0) {
         if (fp32) {
             if (has_p) hipLaunchKernelGGL((k_batch_assemble<float, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
             else hipLaunchKernelGGL((k_batch_assemble<float, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
@@ -397,9 +487,14 @@ extern "C" int lesasm_batch_create(lesasm_mesh *const *meshes, int n, lesasm_bat
     LESASM_HIP_TRY(hipGetDeviceProperties(&prop, dev));
     b->n_cu = prop.multiProcessorCount;
     int st;
-    if ((st = balloc(b, &b->d_call, 1)) || (st = balloc(b, &b->d_head, 1))) return st;
+    if ((st = balloc(b, &b->d_call, 1)) || (st = balloc(b, &b->d_head, kHeads))) return st;
     LESASM_HIP_TRY(hipEventCreate(&b->ev0));
     LESASM_HIP_TRY(hipEventCreate(&b->ev1));
+    LESASM_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    for (int i = 0; i < 3; ++i) {
+        LESASM_HIP_TRY(hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming));
+        LESASM_HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
+    }
     b->chunk = meshes[0]->chunk_elems;
     if ((st = build_tables(b)) || (st = build_work(b))) return st;
     guard.p = nullptr;
@@ -433,6 +528,19 @@ extern "C" int lesasm_batch_get_config(const lesasm_batch *b, int *chunk, int *o
     return LESASM_OK;
 }
 
+extern "C" int lesasm_batch_set_per_type(lesasm_batch *b, int per_type) {
+    if (!b) return fail(LESASM_E_INVALID_ARG, "batch_set_per_type: batch is NULL");
+    if (per_type != 0 && per_type != 1) return fail(LESASM_E_UNSUPPORTED, "batch_set_per_type: 0 or 1");
+    b->per_type = per_type;
+    return rebuild(b);
+}
+
+extern "C" int lesasm_batch_get_per_type(const lesasm_batch *b, int *per_type) {
+    if (!b || !per_type) return fail(LESASM_E_INVALID_ARG, "batch_get_per_type: NULL argument");
+    *per_type = b->per_type;
+    return LESASM_OK;
+}
+
 extern "C" int lesasm_batch_assemble(lesasm_batch *b, const double *const *d_u, const double *const *d_p,
                                      const double *nu, double *const *d_rhs, void *stream) {
     if (!b || !d_u || !nu || !d_rhs) return fail(LESASM_E_INVALID_ARG, "batch_assemble: NULL argument");
@@ -454,20 +562,21 @@ extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, cons
                                  double *best_ms) {
     if (!b || !d_u || !nu || !d_rhs || reps < 1) return fail(LESASM_E_INVALID_ARG, "batch_tune: bad argument");
     std::ostringstream sig;
-    sig << "cu" << b->n_cu;
+    sig << "v2_cu" << b->n_cu;
     for (lesasm_mesh *m : b->meshes)
         for (int k = 0; k < kNumCat; ++k) sig << "_" << m->cat[k].n;
     const std::string key = sig.str();
     if (cache_path && *cache_path) {
         std::ifstream in(cache_path);
         std::string k;
-        int c, o, g;
+        int c, o, g, t;
         double ms;
-        while (in >> k >> c >> o >> g >> ms)
+        while (in >> k >> c >> o >> g >> t >> ms)
             if (k == key) {
                 b->chunk = c;
                 b->order = o;
                 b->grid_per_cu = g;
+                b->per_type = t;
                 int st = rebuild(b);
                 if (st) return st;
                 if (best_ms) *best_ms = ms;
@@ -483,43 +592,46 @@ extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, cons
     const int orders[] = {LESASM_ORDER_MESH, LESASM_ORDER_LARGEST_FIRST, LESASM_ORDER_INTERLEAVED};
     const int grids[] = {2, 4};
     double best = 1e30;
-    int bc = b->chunk, bo = b->order, bg = b->grid_per_cu;
-    for (int c : chunks) {
-        b->chunk = c;
+    int bc = b->chunk, bo = b->order, bg = b->grid_per_cu, bt = b->per_type;
+    for (int c : chunks)
         for (int o : orders)
-            for (int g : grids) {
-                b->order = o;
-                b->grid_per_cu = g;
-                if ((st = rebuild(b))) return st;
-                std::vector<float> t;
-                for (int r = 0; r < reps + 1; ++r) {
-                    LESASM_HIP_TRY(hipEventRecord(b->ev0, 0));
-                    if ((st = batch_launch(b, call, d_p != nullptr, fp32, 0))) return st;
-                    LESASM_HIP_TRY(hipEventRecord(b->ev1, 0));
-                    LESASM_HIP_TRY(hipEventSynchronize(b->ev1));
-                    float ms = 0;
-                    LESASM_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-                    if (r) t.push_back(ms);  // first run warms up
+            for (int g : grids)
+                for (int pt = 0; pt < 2; ++pt) {
+                    b->chunk = c;
+                    b->order = o;
+                    b->grid_per_cu = g;
+                    b->per_type = pt;
+                    if ((st = rebuild(b))) return st;
+                    std::vector<float> t;
+                    for (int r = 0; r < reps + 1; ++r) {
+                        LESASM_HIP_TRY(hipEventRecord(b->ev0, 0));
+                        if ((st = batch_launch(b, call, d_p != nullptr, fp32, 0))) return st;
+                        LESASM_HIP_TRY(hipEventRecord(b->ev1, 0));
+                        LESASM_HIP_TRY(hipEventSynchronize(b->ev1));
+                        float ms = 0;
+                        LESASM_HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+                        if (r) t.push_back(ms);  // first run warms up
+                    }
+                    std::sort(t.begin(), t.end());
+                    const double med = t[t.size() / 2];
+                    if (med < best) {
+                        best = med;
+                        bc = c;
+                        bo = o;
+                        bg = g;
+                        bt = pt;
+                    }
                 }
-                std::sort(t.begin(), t.end());
-                const double med = t[t.size() / 2];
-                if (med < best) {
-                    best = med;
-                    bc = c;
-                    bo = o;
-                    bg = g;
-                }
-            }
-    }
     b->chunk = bc;
     b->order = bo;
     b->grid_per_cu = bg;
+    b->per_type = bt;
     if ((st = rebuild(b))) return st;
     b->last_tune_ms = best;
     if (best_ms) *best_ms = best;
     if (cache_path && *cache_path) {
         std::ofstream outf(cache_path, std::ios::app);
-        outf << key << " " << bc << " " << bo << " " << bg << " " << best << "\n";
+        outf << key << " " << bc << " " << bo << " " << bg << " " << bt << " " << best << "\n";
     }
     return LESASM_OK;
 }

@@ -39,6 +39,7 @@ EXPORTS = [
     "lesasm_mlp_set_params", "lesasm_mlp_loss_grad", "lesasm_mlp_adam", "lesasm_mlp_train_step", "lesasm_mlp_commit",
     "lesasm_mlp_forward_f32", "lesasm_mlp_infer_bf16", "lesasm_mesh_set_closure", "lesasm_mesh_closure_fallbacks",
     "lesasm_element_centroids", "lesasm_sfc_workspace_bytes", "lesasm_sfc_partition", "lesasm_balance_update",
+    "lesasm_batch_set_per_type", "lesasm_batch_get_per_type",
 ]
 MLP_PARAMS = 5254
 ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
@@ -108,6 +109,7 @@ def load(path: str = LIB_PATH):
         "lesasm_element_centroids": [I64, P, P, I64, I64, P, P, P, P, P],
         "lesasm_sfc_workspace_bytes": [I64, I, I, P], "lesasm_sfc_partition": [I64, P, P, I, P, I, P, ctypes.c_size_t, P, P],
         "lesasm_balance_update": [I, I, P, P, D, P],
+        "lesasm_batch_set_per_type": [P, I], "lesasm_batch_get_per_type": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -448,10 +450,15 @@ class Batch:
     def configure(self, chunk: int = 0, order: int = ORDER_MESH, grid_per_cu: int = 2):
         check(load().lesasm_batch_configure(self._h, int(chunk), int(order), int(grid_per_cu)))
 
+    def set_per_type(self, on: bool):
+        """One persistent kernel per element type (True) or one for all (False)."""
+        check(load().lesasm_batch_set_per_type(self._h, 1 if on else 0))
+
     def config(self) -> dict:
-        c, o, g, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        c, o, g, n, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(load().lesasm_batch_get_config(self._h, ctypes.byref(c), ctypes.byref(o), ctypes.byref(g), ctypes.byref(n)))
-        return {"chunk": c.value, "order": o.value, "grid_per_cu": g.value, "items": n.value}
+        check(load().lesasm_batch_get_per_type(self._h, ctypes.byref(t)))
+        return {"chunk": c.value, "order": o.value, "grid_per_cu": g.value, "items": n.value, "per_type": t.value}
 
     def _args(self, us, ps, nus):
         nu = (ctypes.c_double * len(nus))(*[float(v) for v in nus])

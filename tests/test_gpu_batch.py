@@ -51,16 +51,20 @@ def batch_setup(torch_cuda):
 
 @pytest.mark.parametrize("chunk", [0, 64, 512])
 @pytest.mark.parametrize("order", [0, 1, 2])
-def test_batch_matches_oracle(torch_cuda, batch_setup, chunk, order):
+@pytest.mark.parametrize("per_type", [False, True])
+def test_batch_matches_oracle(torch_cuda, batch_setup, chunk, order, per_type):
     torch = torch_cuda
     cases, meshes, us, ps, refs, b = batch_setup
+    b.set_per_type(per_type)
     b.configure(chunk=chunk, order=order, grid_per_cu=2)
+    assert b.config()["per_type"] == int(per_type)
     outs = [torch.full_like(u, float("nan")) for u in us]
     b.assemble(us, ps, [c.nu for c in cases], outs)
     torch.cuda.synchronize()
     for c, m, o, ref in zip(cases, meshes, outs, refs):
         got = m.to_user(o).cpu().numpy()
-        assert rel(got, ref) < TOL64, (c.name, chunk, order)
+        assert rel(got, ref) < TOL64, (c.name, chunk, order, per_type)
+    b.set_per_type(False)
 
 
 def test_batch_equals_per_mesh_assembly(torch_cuda, batch_setup):
@@ -107,11 +111,14 @@ def test_rk3_stages_match_oracle(torch_cuda, batch_setup):
         assert rel(m.to_user(uw).cpu().numpy(), ref) < TOL64
 
 
-def test_graph_replays_match_eager(torch_cuda, batch_setup):
+@pytest.mark.parametrize("per_type", [False, True])
+def test_graph_replays_match_eager(torch_cuda, batch_setup, per_type):
     """Replay the captured step several times with eager work and
-    synchronisation in between; every replay equals the eager sequence."""
+    synchronisation in between; every replay equals the eager sequence
+    (with one kernel per type, the capture holds the forked streams)."""
     torch = torch_cuda
     cases, meshes, us, ps, refs, b = batch_setup
+    b.set_per_type(per_type)
     b.configure(chunk=0, order=1, grid_per_cu=2)
     nus = [c.nu for c in cases]
     dt = 0.005
@@ -127,3 +134,4 @@ def test_graph_replays_match_eager(torch_cuda, batch_setup):
         torch.cuda.synchronize()
         for g, e in zip(ug, ue):
             assert rel(g.cpu().numpy(), e.cpu().numpy()) < 1e-13, rep
+    b.set_per_type(False)
