@@ -1,0 +1,71 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times (default mesh options: staged scatter, concurrent element-type
+kernels): the 20 M-element hybrid box (FP64 and FP32 contractions) and the
+20.25 M-element all-tetrahedron box.  The oracle cannot assemble these
+meshes within a test's time, so outputs are sampled: 3000 seeded random
+nodes, whose every incident element is assembled by the oracle (the sampled
+nodes' residuals are then complete and exact)."""
+import numpy as np
+import pytest
+
+from paper_2005_05899_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _sampled_reference(case, nodes):
+    """Oracle residual at `nodes` (user field ids): assemble every element
+    touching them as a mesh of its own."""
+    import oracle
+    m = case.mesh
+    fmap = m.field_node if m.field_node is not None else None
+    conn_f = fmap[m.conn] if fmap is not None else m.conn
+    hit = np.isin(conn_f, nodes)
+    elem_of = np.repeat(np.arange(m.n_elems), np.diff(m.conn_offsets))
+    elems = np.unique(elem_of[hit])
+    sub, fids = mg.submesh(m, elems)
+    r = oracle.assemble(sub, case.u[fids], None if case.p is None else case.p[fids], case.nu, case.vreman_c)
+    pos = np.searchsorted(fids, nodes)
+    assert np.array_equal(fids[pos], nodes)
+    return r[pos], len(elems)
+
+
+def _check(torch, case, precision, tol, seed):
+    from paper_2005_05899_amd import lesasm
+    m = lesasm.Mesh.from_arrays(case.mesh, case.vreman_c)
+    m.precision = precision
+    u = m.to_internal(torch.from_numpy(case.u).cuda())
+    p = None if case.p is None else m.to_internal(torch.from_numpy(case.p).cuda())
+    got = m.to_user(m.assemble_momentum_rhs(u, p, case.nu)).cpu().numpy()
+    m.close()
+    nodes = np.sort(np.random.default_rng(seed).choice(case.mesh.n_field_nodes, 3000, replace=False))
+    ref, n_el = _sampled_reference(case, nodes)
+    scale = np.abs(ref).max(axis=0)
+    err = (np.abs(got[nodes] - ref) / scale).max()
+    print(f"  {case.name} {precision}: {n_el} elements around 3000 nodes, max error {err:.3e}", flush=True)
+    assert err <= tol, err
+
+
+@pytest.fixture(scope="module")
+def hybrid20m():
+    return mg.hybrid_20m_case()
+
+
+def test_hybrid_20m_fp64_sampled(torch_cuda, hybrid20m):
+    _check(torch_cuda, hybrid20m, "fp64", 1e-12, 1)
+
+
+def test_hybrid_20m_fp32_sampled(torch_cuda, hybrid20m):
+    _check(torch_cuda, hybrid20m, "fp32", 1e-5, 2)
+
+
+def test_tet_20m_fp64_sampled(torch_cuda):
+    _check(torch_cuda, mg.tet_case(150), "fp64", 1e-12, 3)
