@@ -69,3 +69,39 @@ def test_hybrid_20m_fp32_sampled(torch_cuda, hybrid20m):
 
 def test_tet_20m_fp64_sampled(torch_cuda):
     _check(torch_cuda, mg.tet_case(150), "fp64", 1e-12, 3)
+
+
+def test_learned_closure_20m_fp32_sampled(torch_cuda, hybrid20m):
+    # the committed, trained network in the fused closure (FP32 contractions,
+    # 5 % fallback rule), as the 20 M workload runs it; the closure oracle
+    # decides the fallback per element, so it too works on the sampled region
+    import json
+    import os
+    from oracle import closure
+    from oracle import mlp as omlp
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    data = os.path.join(os.path.dirname(lesasm.__file__), "data")
+    flat = np.load(os.path.join(data, "closure_weights.npy"))
+    delta_ref = json.load(open(os.path.join(data, "closure_weights.json")))["delta_ref"]
+    case = hybrid20m
+    m = lesasm.Mesh.from_arrays(case.mesh, case.vreman_c)
+    m.precision = "fp32"
+    net = lesasm.MLP(flat.astype(np.float32))
+    lesasm.set_closure(m, net, delta_ref, 0.05)
+    u = m.to_internal(torch.from_numpy(case.u).cuda())
+    p = m.to_internal(torch.from_numpy(case.p).cuda())
+    got = m.to_user(m.assemble_momentum_rhs(u, p, case.nu)).cpu().numpy()
+    m.close()
+    net.close()
+    nodes = np.sort(np.random.default_rng(4).choice(case.mesh.n_field_nodes, 1000, replace=False))
+    mm = case.mesh
+    hit = np.isin(mm.conn, nodes)
+    elem_of = np.repeat(np.arange(mm.n_elems), np.diff(mm.conn_offsets))
+    sub, fids = mg.submesh(mm, np.unique(elem_of[hit]))
+    params = {k: v.astype(np.float32).astype(np.float64) for k, v in omlp.unflatten(flat.astype(np.float64)).items()}
+    ref, use, eps = closure.assemble(sub, case.u[fids], case.p[fids], case.nu, case.vreman_c, params, delta_ref, 0.05)
+    pos = np.searchsorted(fids, nodes)
+    err = np.linalg.norm(got[nodes] - ref[pos], axis=0) / np.linalg.norm(ref[pos], axis=0)
+    print(f"  closure 20M fp32: {sub.n_elems} elements, {1 - use.mean():.2f} fall back, rel L2 per field {err}", flush=True)
+    assert (err <= 1e-3).all(), err
