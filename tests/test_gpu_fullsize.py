@@ -105,3 +105,41 @@ def test_learned_closure_20m_fp32_sampled(torch_cuda, hybrid20m):
     err = np.linalg.norm(got[nodes] - ref[pos], axis=0) / np.linalg.norm(ref[pos], axis=0)
     print(f"  closure 20M fp32: {sub.n_elems} elements, {1 - use.mean():.2f} fall back, rel L2 per field {err}", flush=True)
     assert (err <= 1e-3).all(), err
+
+
+def test_batch_64_partitions_sampled(torch_cuda):
+    # the batched workload (64 partitions, about 25 M elements) in the
+    # configuration the autotuner picks on the MI355X (one persistent kernel
+    # per element type, chunks of 512, 2 workgroups per CU); 100 sampled
+    # nodes per partition against the oracle
+    import oracle
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    sizes = mg.partition_sizes(64, seed=6)
+    cases, meshes, us, ps = [], [], [], []
+    for i, e in enumerate(sizes):
+        c = mg.hybrid_case(int(e), seed_mesh=6 + i, seed_u=100 + i, seed_p=200 + i, n_modes=64)
+        m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+        cases.append(c)
+        meshes.append(m)
+        us.append(m.to_internal(torch.from_numpy(c.u).cuda()))
+        ps.append(m.to_internal(torch.from_numpy(c.p).cuda()))
+    print(f"  batch of {len(meshes)} partitions, {sum(c.mesh.n_elems for c in cases)} elements", flush=True)
+    b = lesasm.Batch(meshes)
+    b.set_per_type(True)
+    b.configure(chunk=512, order=0, grid_per_cu=2)
+    outs = [torch.full_like(u, float("nan")) for u in us]
+    b.assemble(us, ps, [c.nu for c in cases], outs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (c, m, o) in enumerate(zip(cases, meshes, outs)):
+        got = m.to_user(o).cpu().numpy()
+        assert np.isfinite(got).all()
+        nodes = np.sort(np.random.default_rng(100 + i).choice(c.mesh.n_field_nodes, 100, replace=False))
+        ref, _ = _sampled_reference(c, nodes)
+        worst = max(worst, float((np.abs(got[nodes] - ref) / np.abs(ref).max(axis=0)).max()))
+    print(f"  worst sampled error over the partitions {worst:.3e}", flush=True)
+    assert worst <= 1e-12
+    b.close()
+    for m in meshes:
+        m.close()
