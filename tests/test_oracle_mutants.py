@@ -118,3 +118,43 @@ def test_partition_pins_catch_mutant(name, tmp_path):
     assert src.count(old) >= 1, name
     r = _run_partition_pins(src.replace(old, new), tmp_path)
     assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
+
+
+# ---- the conjugate-gradient oracle (Python) -----------------------------------
+
+CG_SRC = os.path.join(ROOT, "oracle", "cg.py")
+CG_PINS = "tests/test_oracle_cg.py"
+
+CG_MUTANTS = {
+    "beta_inverted": ("p = z + (rz_new / rz) * p", "p = z + (rz / rz_new) * p"),
+    "direction_from_unpreconditioned_residual": ("p = z + (rz_new / rz) * p", "p = r + (rz_new / rz) * p"),
+    "alpha_from_r_dot_r": ("alpha = rz / float(p @ q)", "alpha = float(r @ r) / float(p @ q)"),
+    "residual_update_sign": ("r = r - alpha * q", "r = r + alpha * q"),
+    "rz_never_advanced": ("            rz = rz_new\n", "            pass\n"),
+    "preconditioner_not_inverted": ("dinv = 1.0 / K.diagonal()", "dinv = K.diagonal()"),
+    "right_hand_side_not_projected": ("        b = b - b.mean()\n", "        b = b + 0.0\n"),
+    "solution_not_projected": ("        x = x - x.mean()\n", "        x = x + 0.0\n"),
+    "stops_on_unchecked_iterations": ("if it % check_every == 0 or it == maxit:", "if True:"),
+}
+
+
+def _run_cg_pins(src_text, tmp_path):
+    mut = tmp_path / "cg_variant.py"
+    mut.write_text(src_text)
+    env = dict(os.environ, LESASM_CG_ORACLE=str(mut))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", CG_PINS],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_cg_unmodified_copy_passes(tmp_path):
+    r = _run_cg_pins(open(CG_SRC).read(), tmp_path)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(CG_MUTANTS))
+def test_cg_pins_catch_mutant(name, tmp_path):
+    old, new = CG_MUTANTS[name]
+    src = open(CG_SRC).read()
+    assert src.count(old) == 1, name
+    r = _run_cg_pins(src.replace(old, new), tmp_path)
+    assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
