@@ -51,6 +51,7 @@ WEIGHTS_META = os.path.join(ROOT, "paper_2005_05899_amd", "data", "closure_weigh
 ASSEMBLY_SOURCES = ("csrc/assemble.hip", "csrc/element.hpp", "csrc/modal.hpp", "csrc/refelem.hpp", "csrc/mlp.hpp",
                     "csrc/common.hpp")
 PARTITION_SOURCES = ("csrc/partition.hip", "csrc/common.hpp")
+CG_SOURCES = ("csrc/stepper.hip", "csrc/common.hpp")
 
 
 def source_hash(files=ASSEMBLY_SOURCES) -> str:
@@ -523,12 +524,104 @@ def run_precision(args):
     mesh.close()
 
 
+def spmv_bytes(nnz: int, n: int) -> int:
+    """Algorithmic bytes of one product q = K p: 12 B per nonzero (value,
+    column index), p read once and q written (8 B per row each); the storage
+    format's own overhead (row pointers, padding) is not counted."""
+    return 12 * nnz + 16 * n
+
+
 def cg_bytes_per_iteration(nnz: int, n: int) -> int:
-    """Algorithmic bytes of one Jacobi-CG iteration: the SpMV reads 12 B per
-    nonzero (value, column), 4 B per row pointer and p once, writes q; the
-    update reads x, p, r, q and the diagonal and writes x, r, z; the direction
-    reads z, p and writes p (8 B per row each)."""
-    return 12 * nnz + 4 * (n + 1) + 8 * n * (2 + 8 + 3)
+    """Algorithmic bytes of one Jacobi-CG iteration: the SpMV; the update reads
+    x, p, r, q and the diagonal and writes x, r, z; the direction reads z, p
+    and writes p (8 B per row each)."""
+    return spmv_bytes(nnz, n) + 8 * n * (8 + 3)
+
+
+def run_cg(args):
+    """The pressure solver (Section 3.2, Algorithm 1: Jacobi-preconditioned CG,
+    one SpMV and two dot products per iteration) on the Laplacian of the 20 M
+    hybrid box (the mesh of the precision workload).  A step is one CG
+    iteration; --steps iterations run in one solve whose tolerance is never
+    reached; right-hand side and matrix resident in HBM.  The dominant kernel
+    is the SpMV, timed on its own by back-to-back products."""
+    import torch
+    from paper_2005_05899_amd import lesasm, meshgen
+    torch.cuda.set_device(0)
+    layers = meshgen.hybrid_layers(205 * 205, 20_000_000)
+    mg_mesh = meshgen.hybrid_box(205, 205, layers, seed=4)
+    mesh = lesasm.Mesh.from_arrays(mg_mesh, 0.1)
+    n = mesh.n_field_nodes
+    t0 = time.perf_counter()
+    st = lesasm.Stepper(mesh, 1.5e-5, 1e-3, rtol=1e-300, maxit=args.steps)
+    t_setup = time.perf_counter() - t0
+    print(f"  stepper set up in {t_setup:.1f} s ({n} rows)", file=sys.stderr, flush=True)
+    nnz = ctypes.c_int64()
+    lesasm.check(lesasm.load().lesasm_stepper_laplacian(st._h, None, None, None, ctypes.byref(nnz)))
+    nnz = nnz.value
+    entries = st.sell_entries()
+    b = mesh.to_internal(torch.from_numpy(np.random.default_rng(21).standard_normal(n)).cuda())
+    if args.warmup:
+        st.pressure_solve(b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x = st.pressure_solve(b)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    it, res = st.stats()
+    assert it == args.steps and np.isfinite(res) and torch.isfinite(x).all()
+    # the SpMV alone: events on the stream the library launches on
+    q = torch.empty_like(b)
+    for _ in range(max(args.warmup, 1)):
+        st.spmv(x, q)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(args.steps):
+        st.spmv(x, q)
+    ev[1].record()
+    ev[1].synchronize()
+    ms_spmv = ev[0].elapsed_time(ev[1]) / args.steps
+    print(f"  {1e3 * el / it:.4f} ms per CG iteration, SpMV {ms_spmv:.4f} ms", file=sys.stderr, flush=True)
+    sb = spmv_bytes(nnz, n)
+    cb = cg_bytes_per_iteration(nnz, n)
+    ms_it = 1e3 * el / it
+    tr = traffic_from_profiles("all", "cg20m", "k_spmv_sell_dot", CG_SOURCES)
+    out = {
+        "metric": "pressure-CG row-iterations/s (Jacobi-PCG)", "value": n * it / el, "unit": "row-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_it, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded hybrid box, random b)",
+        "config": {"workload": f"Laplacian of the hybrid box 205 x 205 cells ({mg_mesh.n_elems} elements): "
+                               f"{n} rows, {nnz} nonzeros; {it} iterations per solve"},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv_sell_dot", "achieved": sb / ms_spmv / 1e6, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": sb / ms_spmv / 1e6 / HBM_PEAK_GBS,
+                     "traffic": None if tr is None else tr["bytes_per_launch"], "bytes_per_launch": sb,
+                     "avg_ms": ms_spmv},
+        "source_hash": source_hash(CG_SOURCES),
+        "iteration": {"algorithmic_bytes": cb, "GBs": cb / ms_it / 1e6, "frac_of_hbm": cb / ms_it / 1e6 / HBM_PEAK_GBS},
+        "sliced_ellpack_entries": entries, "padding_fraction": entries / nnz - 1.0,
+        "relative_residual_after": res, "setup_seconds": t_setup,
+    }
+    st.close()
+    mesh.close()
+    if not args.no_cpu_baseline:
+        # the oracle's CG on a smaller box of the same construction (its
+        # Laplacian assembly in the oracle takes minutes at 20 M); the rate is
+        # per row-iteration, which scales linearly with the matrix
+        from oracle import cg, step
+        sm = meshgen.hybrid_case(500_000, seed_mesh=4, with_p=False, n_modes=8).mesh
+        K = step.laplacian(sm)
+        bs = np.random.default_rng(22).standard_normal(K.shape[0])
+        iters = 0
+        t2 = time.perf_counter()
+        while time.perf_counter() - t2 < 10.0:
+            cg.jacobi_pcg(K, bs, 100, rtol=0.0)
+            iters += 100
+        dt = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": K.shape[0] * iters / dt, "unit": "row-iterations/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{iters} oracle CG iterations on the Laplacian of a {sm.n_elems}-element "
+                                         f"hybrid box ({K.shape[0]} rows, {K.nnz} nonzeros), {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
 
 
 def partition_bytes(mesh, nbins: int) -> dict:
@@ -723,7 +816,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100, help="untimed steps first (lets the clocks settle)")
     ap.add_argument("--workload", choices=["hybrid2m", "tet20m", "batch64", "precision20m", "copy", "partition20m",
-                                           "balance8"], default="hybrid2m")
+                                           "balance8", "cg20m"], default="hybrid2m")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--scatter", choices=["staged", "chunk_atomic", "colour", "direct"], default="staged")
     ap.add_argument("--chunk", type=int, default=None, help="elements per chunk (chunked scatters)")
@@ -746,6 +839,8 @@ def main():
         run_partition(args)
     elif args.workload == "balance8":
         run_balance(args)
+    elif args.workload == "cg20m":
+        run_cg(args)
     else:
         run_main(args)
 

@@ -222,7 +222,8 @@ int lesasm_gradient(lesasm_mesh *mesh, const double *d_p, double *d_out, void *s
 typedef struct lesasm_stepper lesasm_stepper;
 
 /* Time stepper of Algorithm 1 on a mesh (which must outlive it): assembles the
- * Laplacian K_ab = int grad N_a . grad N_b dV once (CSR on the device), keeps
+ * Laplacian K_ab = int grad N_a . grad N_b dV once (CSR on the device, plus a
+ * sliced-ELLPACK copy for the CG's products, see lesasm_stepper_spmv), keeps
  * work vectors, and runs per step three explicit Runge-Kutta stages (Heun's
  * third-order tableau: c = (0, 1/3, 2/3), a21 = 1/3, a32 = 2/3,
  * b = (1/4, 0, 3/4)) and one pressure solve by Jacobi-preconditioned CG to
@@ -251,6 +252,19 @@ int lesasm_stepper_stats(const lesasm_stepper *stepper, int *cg_iters, double *c
 /* Copy the assembled Laplacian to host arrays (rowptr[n_field_nodes+1],
  * col[nnz], val[nnz], any of them may be NULL); *nnz receives the count. */
 int lesasm_stepper_laplacian(lesasm_stepper *stepper, int32_t *rowptr, int32_t *col, double *val, int64_t *nnz);
+
+/* q = K p with the Laplacian above, by the kernel the pressure CG runs (a
+ * sliced-ELLPACK copy of K: slices of 64 consecutive rows, each padded to its
+ * longest row and stored column-major; the CSR form if that copy would exceed
+ * 2^31 entries).  d_p and d_q are device arrays of n_field_nodes doubles in
+ * internal order, must not alias (LESASM_E_INVALID_ARG).  Asynchronous on
+ * `stream`; the stepper's reduction buffer is written, so calls must not
+ * overlap a pressure solve or step of the same stepper. */
+int lesasm_stepper_spmv(lesasm_stepper *stepper, const double *d_p, double *d_q, void *stream);
+
+/* Stored entries of the sliced-ELLPACK copy of K (nonzeros plus padding; 0 if
+ * the CSR form serves the CG). */
+int lesasm_stepper_sell_entries(const lesasm_stepper *stepper, int64_t *entries);
 
 /* ---- batches of mesh partitions ---------------------------------------- */
 

@@ -303,6 +303,72 @@ __global__ __launch_bounds__(256) void k_spmv_dot(const int32_t *__restrict__ ro
     block_sum_256(pq, sh, partial + blockIdx.x);
 }
 
+#ifndef LESASM_CG_SELL
+#define LESASM_CG_SELL 1
+#endif
+constexpr int kSlice = 64;  // rows per slice of the sliced-ELLPACK copy (one wavefront)
+#ifndef LESASM_SELL_UNROLL
+#define LESASM_SELL_UNROLL 4
+#endif
+#ifndef LESASM_SELL_NT
+#define LESASM_SELL_NT 1
+#endif
+constexpr int kSellUnroll = LESASM_SELL_UNROLL;  // row entries in flight per lane
+// the matrix is read once per SpMV: streamed past the caches when LESASM_SELL_NT
+template <class T> __device__ __forceinline__ T sell_load(const T *a) {
+    if (LESASM_SELL_NT) return __builtin_nontemporal_load(a);
+    return *a;
+}
+
+// q = K p on the sliced-ELLPACK copy of K: slice s holds rows 64 s .. 64 s +
+// 63, padded to its longest row and stored column-major, so entry j of all 64
+// rows is one coalesced load; lane l adds row 64 s + l's entries in column
+// order (four in flight).  Padding entries hold value 0 and a valid column.
+// One wavefront per slice, slices in a fixed grid-stride order; partial[b] =
+// block sums of p.q.
+__global__ __launch_bounds__(256) void k_spmv_sell_dot(const int32_t *__restrict__ soff,
+                                                       const int32_t *__restrict__ scol,
+                                                       const double *__restrict__ sval, const double *__restrict__ p,
+                                                       double *__restrict__ q, int n, int nslices,
+                                                       double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const int lane = threadIdx.x % kSlice, wave = threadIdx.x / kSlice;
+    const int waves = 256 / kSlice;
+    double pq = 0.0;
+    for (int sl = blockIdx.x * waves + wave; sl < nslices; sl += gridDim.x * waves) {
+        const int o0 = soff[sl], w = (soff[sl + 1] - o0) / kSlice;
+        const int32_t *cc = scol + o0 + lane;
+        const double *vv = sval + o0 + lane;
+        double s = 0.0;
+        int j = 0;
+        for (; j + kSellUnroll <= w; j += kSellUnroll) {
+            int c[kSellUnroll];
+            double v[kSellUnroll];
+#pragma unroll
+            for (int k = 0; k < kSellUnroll; ++k) {
+                c[k] = sell_load(cc + kSlice * (j + k));
+                v[k] = sell_load(vv + kSlice * (j + k));
+            }
+#pragma unroll
+            for (int k = 0; k < kSellUnroll; ++k) s += v[k] * p[c[k]];
+        }
+        for (; j < w; ++j) s += sell_load(vv + kSlice * j) * p[sell_load(cc + kSlice * j)];
+        const int row = sl * kSlice + lane;
+        if (row < n) {
+            q[row] = s;
+            pq += s * p[row];
+        }
+    }
+    block_sum_256(pq, sh, partial + blockIdx.x);
+}
+
+// sliced-ELLPACK values from the assembled CSR values (src < 0: padding)
+__global__ void k_sell_fill(const int32_t *__restrict__ src, const double *__restrict__ val, double *__restrict__ sval,
+                            int64_t total) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        sval[i] = src[i] >= 0 ? val[src[i]] : 0.0;
+}
+
 // alpha = rz / pq;  x += alpha p;  r -= alpha q;  z = r / diag;
 // partial[2b] = block sums of r.z, partial[2b+1] = of r.r
 __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ x, double *__restrict__ r,
@@ -447,6 +513,11 @@ struct lesasm_stepper {
     int last_iters = 0;
     double last_res = 0.0;
     int64_t nnz = 0;
+    // sliced-ELLPACK copy of K for the CG's SpMV (empty if not built)
+    int32_t *soff = nullptr, *scol = nullptr;
+    double *sval = nullptr;
+    int nslices = 0;
+    int64_t sell_entries = 0;
 };
 
 namespace {
@@ -504,8 +575,12 @@ int pressure_solve(lesasm_stepper *st, const double *b_in, double *x, hipStream_
         // while a kernel may still read it.
         int i_rz = S_RZ, i_rzn = S_RZN;
         for (it = 1; it <= st->maxit; ++it) {
-            hipLaunchKernelGGL(k_spmv_dot, dim3(kCgBlocks), dim3(256), 0, s, st->rowptr, st->col, st->val, st->pv,
-                               st->q, n, st->partial);
+            if (st->sval)
+                hipLaunchKernelGGL(k_spmv_sell_dot, dim3(kCgBlocks), dim3(256), 0, s, st->soff, st->scol, st->sval,
+                                   st->pv, st->q, n, st->nslices, st->partial);
+            else
+                hipLaunchKernelGGL(k_spmv_dot, dim3(kCgBlocks), dim3(256), 0, s, st->rowptr, st->col, st->val, st->pv,
+                                   st->q, n, st->partial);
             hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 1, 1,
                                st->scal + S_PQ, st->scal + S_PQ);
             hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(256), 0, s, x, st->r, st->z, st->pv, st->q,
@@ -634,6 +709,53 @@ extern "C" int lesasm_stepper_create(lesasm_mesh *m, double nu, double dt, doubl
                             (const int32_t *)st->col, st->val);
         hipLaunchKernelGGL(k_diag, dim3((n + 255) / 256), dim3(256), 0, 0, st->rowptr, st->col, st->val, st->diag, n);
         LESASM_HIP_TRY(hipGetLastError());
+        if (LESASM_CG_SELL) {
+            // slices of kSlice rows, each padded to its longest row, column-major
+            const int ns = (n + kSlice - 1) / kSlice;
+            std::vector<int32_t> soff(ns + 1, 0);
+            int64_t total = 0;
+            for (int sl = 0; sl < ns; ++sl) {
+                int w = 0;
+                for (int r = sl * kSlice; r < std::min(n, (sl + 1) * kSlice); ++r) w = std::max(w, rowptr[r + 1] - rowptr[r]);
+                total += (int64_t)w * kSlice;
+                soff[sl + 1] = (int32_t)std::min<int64_t>(total, INT32_MAX);
+            }
+            if (total < INT32_MAX) {  // otherwise the CSR kernel serves the CG
+                std::vector<int32_t> scol((size_t)total), src((size_t)total);
+                for (int sl = 0; sl < ns; ++sl) {
+                    const int w = (soff[sl + 1] - soff[sl]) / kSlice;
+                    for (int l = 0; l < kSlice; ++l) {
+                        const int r = sl * kSlice + l;
+                        const int len = r < n ? rowptr[r + 1] - rowptr[r] : 0;
+                        for (int j = 0; j < w; ++j) {
+                            const size_t at = (size_t)soff[sl] + (size_t)j * kSlice + l;
+                            if (j < len) {
+                                scol[at] = col[(size_t)rowptr[r] + j];
+                                src[at] = rowptr[r] + j;
+                            } else {
+                                scol[at] = r < n ? r : 0;
+                                src[at] = -1;
+                            }
+                        }
+                    }
+                }
+                int32_t *d_src = nullptr;
+                if ((rc = salloc(st, &st->soff, soff.size())) || (rc = salloc(st, &st->scol, scol.size())) ||
+                    (rc = salloc(st, &st->sval, scol.size())) || (rc = salloc(st, &d_src, src.size())))
+                    return rc;
+                LESASM_HIP_TRY(hipMemcpy(st->soff, soff.data(), sizeof(int32_t) * soff.size(), hipMemcpyHostToDevice));
+                LESASM_HIP_TRY(hipMemcpy(st->scol, scol.data(), sizeof(int32_t) * scol.size(), hipMemcpyHostToDevice));
+                LESASM_HIP_TRY(hipMemcpy(d_src, src.data(), sizeof(int32_t) * src.size(), hipMemcpyHostToDevice));
+                hipLaunchKernelGGL(k_sell_fill, dim3(grid_for((size_t)total, 256)), dim3(256), 0, 0, d_src, st->val,
+                                   st->sval, total);
+                LESASM_HIP_TRY(hipGetLastError());
+                LESASM_HIP_TRY(hipDeviceSynchronize());
+                st->allocs.erase(std::find(st->allocs.begin(), st->allocs.end(), (void *)d_src));
+                (void)hipFree(d_src);
+                st->nslices = ns;
+                st->sell_entries = total;
+            }
+        }
         LESASM_HIP_TRY(hipDeviceSynchronize());
     }
     guard.p = nullptr;
@@ -652,6 +774,27 @@ extern "C" int lesasm_stepper_laplacian(lesasm_stepper *st, int32_t *rowptr, int
     if (rowptr) LESASM_HIP_TRY(hipMemcpy(rowptr, st->rowptr, sizeof(int32_t) * (st->n + 1), hipMemcpyDeviceToHost));
     if (col) LESASM_HIP_TRY(hipMemcpy(col, st->col, sizeof(int32_t) * st->nnz, hipMemcpyDeviceToHost));
     if (val) LESASM_HIP_TRY(hipMemcpy(val, st->val, sizeof(double) * st->nnz, hipMemcpyDeviceToHost));
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_spmv(lesasm_stepper *st, const double *d_p, double *d_q, void *stream) {
+    if (!st || (st->n && (!d_p || !d_q))) return fail(LESASM_E_INVALID_ARG, "stepper_spmv: NULL argument");
+    if (d_p == d_q) return fail(LESASM_E_INVALID_ARG, "stepper_spmv: p and q must not alias");
+    if (!st->n) return LESASM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (st->sval)
+        hipLaunchKernelGGL(k_spmv_sell_dot, dim3(kCgBlocks), dim3(256), 0, s, st->soff, st->scol, st->sval, d_p, d_q,
+                           st->n, st->nslices, st->partial);
+    else
+        hipLaunchKernelGGL(k_spmv_dot, dim3(kCgBlocks), dim3(256), 0, s, st->rowptr, st->col, st->val, d_p, d_q,
+                           st->n, st->partial);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_sell_entries(const lesasm_stepper *st, int64_t *entries) {
+    if (!st || !entries) return fail(LESASM_E_INVALID_ARG, "stepper_sell_entries: NULL argument");
+    *entries = st->sell_entries;
     return LESASM_OK;
 }
 

@@ -33,6 +33,7 @@ EXPORTS = [
     "lesasm_check", "lesasm_mesh_set_wall", "lesasm_assemble_wall",
     "lesasm_divergence", "lesasm_gradient", "lesasm_stepper_create", "lesasm_stepper_destroy", "lesasm_stepper_step",
     "lesasm_stepper_rk3_stages", "lesasm_pressure_solve", "lesasm_stepper_stats", "lesasm_stepper_laplacian",
+    "lesasm_stepper_spmv", "lesasm_stepper_sell_entries",
     "lesasm_batch_create", "lesasm_batch_destroy", "lesasm_batch_configure", "lesasm_batch_get_config",
     "lesasm_batch_assemble", "lesasm_batch_tune", "lesasm_batch_rk3_graph", "lesasm_batch_rk3_launch",
     "lesasm_batch_rk3_eager", "lesasm_mlp_create", "lesasm_mlp_destroy", "lesasm_mlp_get_params",
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
         "lesasm_stepper_create": [P, D, D, D, I, P], "lesasm_stepper_destroy": [P], "lesasm_stepper_step": [P, P, P, P],
         "lesasm_stepper_rk3_stages": [P, P, P, P, P], "lesasm_pressure_solve": [P, P, P, P],
         "lesasm_stepper_stats": [P, P, P], "lesasm_stepper_laplacian": [P, P, P, P, P],
+        "lesasm_stepper_spmv": [P, P, P, P], "lesasm_stepper_sell_entries": [P, P],
         "lesasm_batch_create": [P, I, P], "lesasm_batch_destroy": [P], "lesasm_batch_configure": [P, I, I, I],
         "lesasm_batch_get_config": [P, P, P, P, P], "lesasm_batch_assemble": [P, P, P, P, P, P],
         "lesasm_batch_tune": [P, P, P, P, P, ctypes.c_char_p, I, P], "lesasm_batch_rk3_graph": [P, P, P, P, D, P],
@@ -318,6 +320,23 @@ class Stepper:
         it, res = ctypes.c_int(), ctypes.c_double()
         check(load().lesasm_stepper_stats(self._h, ctypes.byref(it), ctypes.byref(res)))
         return it.value, res.value
+
+    def spmv(self, p, out=None):
+        """q = K p (internal order) by the pressure CG's product kernel."""
+        self.mesh._field(p)
+        if p.numel() != self.mesh.n_field_nodes:
+            raise ValueError("expected one value per field node")
+        q = torch.empty_like(p) if out is None else self.mesh._field(out)
+        if q.numel() != p.numel():
+            raise ValueError("out must match p")
+        check(load().lesasm_stepper_spmv(self._h, _ptr(p), _ptr(q), _stream()))
+        return q
+
+    def sell_entries(self) -> int:
+        """Stored entries (nonzeros plus padding) of the sliced-ELLPACK copy of K."""
+        e = ctypes.c_int64()
+        check(load().lesasm_stepper_sell_entries(self._h, ctypes.byref(e)))
+        return e.value
 
     def laplacian(self):
         """(rowptr, col, val) host arrays of the assembled K (internal order)."""
