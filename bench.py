@@ -236,7 +236,8 @@ def run_main(args):
                                           concurrent=not args.isolated)
     # the same launches one kernel at a time: isolated durations for the roofline
     el_iso, kt, _ = time_assembly(torch, mesh, u, p, case.nu, args.steps, 2, concurrent=False)
-    el_graph = time_graph_replay(torch, mesh, u, p, case.nu, args.steps, args.warmup)
+    # (left out under --isolated, whose profiles then hold isolated launches only)
+    el_graph = None if args.isolated else time_graph_replay(torch, mesh, u, p, case.nu, args.steps, args.warmup)
     E = m.n_elems
     value = E * args.steps / elapsed
     peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
@@ -298,8 +299,9 @@ def run_main(args):
         "kernels_isolated": per_kernel,
         "kernels_concurrent": per_kernel_conc,
         "isolated_ms_per_step": 1e3 * el_iso / args.steps,
-        "graph_replay": {"value": E * args.steps / el_graph, "ms_per_step": 1e3 * el_graph / args.steps,
-                         "note": "the same assembly captured once in a HIP graph and replayed"},
+        "graph_replay": None if el_graph is None else {
+            "value": E * args.steps / el_graph, "ms_per_step": 1e3 * el_graph / args.steps,
+            "note": "the same assembly captured once in a HIP graph and replayed"},
         "source_hash": source_hash(),
     }
     if args.variants:
