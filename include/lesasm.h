@@ -157,7 +157,8 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
 #define LESASM_OPT_PROFILE 5      /* 1: record HIP events around every kernel launch */
 #define LESASM_OPT_CHUNK 6        /* elements per chunk of the chunked scatters, 32..4096, or 0
                                      (default) for min(512, max(64, 2^floor(log2(n_type/256)))) per
-                                     type; setting it rebuilds the chunks (synchronises) */
+                                     type, 1024 for TET04 when that leaves at least 4096 chunks;
+                                     setting it rebuilds the chunks (synchronises) */
 #define LESASM_OPT_CONCURRENT 7   /* 1 (default): the element-type kernels of one chunked assembly run
                                      concurrently on forked streams (joined before return); 0: one
                                      after another on the caller's stream (isolated kernel timings) */

@@ -195,10 +195,13 @@ template <class T> static void dfree(lesasm_mesh *m, T *&p) {
 // lists are sorted ascending (coalesced loads); a field node is owned by a
 // chunk when all of its incidences in the mesh lie in that chunk.
 
-static int chunk_length(const lesasm_mesh *m, int64_t n) {
+static int chunk_length(const lesasm_mesh *m, int type, int64_t n) {
     if (m->chunk_elems) return m->chunk_elems;
     int ce = 64;
     while (ce < 512 && 2 * ce <= n / 256) ce *= 2;
+    // TET04's light elements gain from longer chunks (fewer shared nodes per
+    // element) once the category still fills the GPU many times over
+    if (type == LESASM_TET04 && ce == 512 && n / 1024 >= 4096) ce = 1024;
     return ce;
 }
 
@@ -222,7 +225,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
     const std::vector<int32_t> &cg = c.h_cg, &cf = periodic ? c.h_cf : c.h_cg;
     const int nnode = c.type;
     const int64_t n = c.n;
-    const int ce = chunk_length(m, n);
+    const int ce = chunk_length(m, c.type, n);
     c.chunk_elems = ce;
     std::vector<int32_t> eoff{0}, goff{0}, foff{0}, gnodes, fnodes;
     std::vector<uint16_t> lg((size_t)nnode * n), lf(periodic ? (size_t)nnode * n : 0);
