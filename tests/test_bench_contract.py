@@ -1,0 +1,67 @@
+"""The benchmark's host logic, on the CPU: the one-GPU rule, the byte counts
+behind the roofline figures (checked on tiny meshes whose counts follow by
+hand), and the source hash that decides whether committed counter summaries
+still describe the kernels."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+from paper_2005_05899_amd import meshgen as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_single_hex_bytes_by_hand():
+    # one HEX08 element: 8 connectivity entries, 8 nodes (24 B geometry,
+    # 24 + 8 + 24 B fields) and one filter width
+    m = mg.uniform_hex_box((1, 1, 1), (1.0, 1.0, 1.0))
+    assert bench.algorithmic_bytes(m, True) == 4 * 8 + 24 * 8 + 8 * (24 + 8 + 24) + 8
+    assert bench.algorithmic_bytes(m, False) == 4 * 8 + 24 * 8 + 8 * (24 + 24) + 8
+    assert bench.per_type_bytes(m, mg.HEX08) == bench.algorithmic_bytes(m, True)
+
+
+def test_per_type_bytes_add_up_to_the_mesh():
+    c = mg.small_hybrid_case(nx=4, ny=3, layers=[(mg.PEN06, 1), (mg.TET04, 1), (mg.PYR05, 1), (mg.HEX08, 1)],
+                             seed=3)
+    parts = sum(bench.per_type_bytes(c.mesh, t) for t in (mg.TET04, mg.PYR05, mg.PEN06, mg.HEX08))
+    assert abs(parts - bench.algorithmic_bytes(c.mesh, True)) <= 1e-6 * parts
+
+
+def test_cg_byte_counts():
+    # 10 nonzeros over 3 rows: values and columns 12 B each, p read and q
+    # written once; the iteration adds 11 vector passes of 8 B per row
+    assert bench.spmv_bytes(10, 3) == 120 + 48
+    assert bench.cg_bytes_per_iteration(10, 3) == 120 + 48 + 8 * 3 * 11
+
+
+def test_source_hash_ignores_comments_and_layout_but_not_code(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_text("// a comment\n__global__ void k(double *a) {\n    a[0] = 1.0; /* set */\n}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    pkg = tmp_path / "paper_2005_05899_amd"
+    pkg.mkdir()
+    (pkg / "k.hip").write_text(src.read_text())
+    h0 = bench.source_hash(("k.hip",))
+    (pkg / "k.hip").write_text("__global__ void k(double *a)\n{\n  a[0] = 1.0;  // set to one\n}\n")
+    assert bench.source_hash(("k.hip",)) == h0
+    (pkg / "k.hip").write_text("__global__ void k(double *a) {\n    a[0] = 2.0;\n}\n")
+    assert bench.source_hash(("k.hip",)) != h0
+
+
+def test_partition_byte_counts():
+    m = mg.uniform_hex_box((2, 1, 1), (2.0, 1.0, 1.0))
+    nb = bench.partition_bytes(m, 8)
+    assert nb["centroids"] == 8 * 3 + 4 * 16 + 24 * 12 + 28 * 2
+    assert nb["split"] == 64 * 2 + 8 * 8 * 6
+    assert np.isfinite(list(nb.values())).all()
