@@ -1,7 +1,7 @@
 """Parity at the full benchmark sizes, in the launch configuration the
 benchmark times (default mesh options: staged scatter, concurrent element-type
 kernels): the 20 M-element hybrid box (FP64 and FP32 contractions) and the
-20.25 M-element all-tetrahedron box.  The oracle cannot assemble these
+20.25 M-element all-tetrahedron box (both precisions).  The oracle cannot assemble these
 meshes within a test's time, so outputs are sampled: 3000 seeded random
 nodes, whose every incident element is assembled by the oracle (the sampled
 nodes' residuals are then complete and exact)."""
@@ -67,8 +67,17 @@ def test_hybrid_20m_fp32_sampled(torch_cuda, hybrid20m):
     _check(torch_cuda, hybrid20m, "fp32", 1e-5, 2)
 
 
-def test_tet_20m_fp64_sampled(torch_cuda):
-    _check(torch_cuda, mg.tet_case(150), "fp64", 1e-12, 3)
+@pytest.fixture(scope="module")
+def tet20m():
+    return mg.tet_case(150)
+
+
+def test_tet_20m_fp64_sampled(torch_cuda, tet20m):
+    _check(torch_cuda, tet20m, "fp64", 1e-12, 3)
+
+
+def test_tet_20m_fp32_sampled(torch_cuda, tet20m):
+    _check(torch_cuda, tet20m, "fp32", 1e-5, 5)
 
 
 def test_learned_closure_20m_fp32_sampled(torch_cuda, hybrid20m):
