@@ -94,6 +94,10 @@ struct ChunkView {
 };
 
 constexpr uint32_t kOwnedBit = 0x80000000u;
+// Vreman-fallback counts of the learned closure: workgroup b adds to slot
+// b % kFallbackSlots (spread over many addresses: one shared counter made
+// every chunk's closing atomic wait on the others)
+constexpr int kFallbackSlots = 4096;
 
 const short *mlp_packed(const lesasm_mlp *p);
 const float *mlp_bias(const lesasm_mlp *p);
@@ -155,7 +159,7 @@ struct lesasm_mesh {
     const lesasm_mlp *mlp = nullptr;
     double delta_ref = 1.0, fallback_tol = 0.05;
     int chunk_max_nodes = 800;              // node cap of a chunk (LDS budget)
-    unsigned long long *d_fallbacks = nullptr;
+    unsigned long long *d_fallbacks = nullptr;  // kFallbackSlots counters
     hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     // wall model (boundary assembly): per wall face, the nodes of the face and
     // of the volume element it bounds, in internal numbering

@@ -427,7 +427,7 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 // staged row (STAGED) or FP64 device atomic otherwise.  LDS layout (doubles):
 //   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
 // Learned closure of a launch: packed weights, filter-width reference and
-// the fallback threshold (squared), plus a counter of Vreman fallbacks.
+// the fallback threshold (squared), plus the counters of Vreman fallbacks.
 struct ClosureView {
     const short *packed;
     const float *bias;
@@ -540,7 +540,7 @@ __device__ __forceinline__ void chunk_body(const ChunkView &c, int j, double *ld
                         unsafeAtomicAdd(sacc + 3 * lf[a] + i, (double)(use_mlp ? acc[a][i] + dacc[a][i] : acc[a][i]));
             }
         }
-        if (fallbacks) atomicAdd(cl->fallbacks, (unsigned long long)fallbacks);
+        if (fallbacks) atomicAdd(cl->fallbacks + (blockIdx.x & (kFallbackSlots - 1)), (unsigned long long)fallbacks);
     }
     __syncthreads();
 

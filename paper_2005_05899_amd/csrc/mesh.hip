@@ -804,9 +804,9 @@ extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, do
     if (cur != m->device) return fail(LESASM_E_STATE, "set_closure: current device differs from the mesh's device");
     LESASM_HIP_TRY(hipDeviceSynchronize());
     if (mlp && !m->d_fallbacks) {
-        int st = dalloc(m, &m->d_fallbacks, 1);
+        int st = dalloc(m, &m->d_fallbacks, kFallbackSlots);
         if (st) return st;
-        LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long)));
+        LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long) * kFallbackSlots));
     }
     m->mlp = mlp;
     m->delta_ref = mlp ? delta_ref : 1.0;
@@ -823,10 +823,13 @@ extern "C" int lesasm_mesh_closure_fallbacks(lesasm_mesh *m, uint64_t *count) {
     if (!m || !count) return fail(LESASM_E_INVALID_ARG, "closure_fallbacks: NULL argument");
     *count = 0;
     if (!m->d_fallbacks) return LESASM_OK;
-    unsigned long long v = 0, zero = 0;
+    std::vector<unsigned long long> v(kFallbackSlots);
     LESASM_HIP_TRY(hipDeviceSynchronize());
-    LESASM_HIP_TRY(hipMemcpy(&v, m->d_fallbacks, sizeof(v), hipMemcpyDeviceToHost));
-    LESASM_HIP_TRY(hipMemcpy(m->d_fallbacks, &zero, sizeof(zero), hipMemcpyHostToDevice));
-    *count = v;
+    LESASM_HIP_TRY(hipMemcpy(v.data(), m->d_fallbacks, sizeof(unsigned long long) * v.size(), hipMemcpyDeviceToHost));
+    LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long) * v.size()));
+    LESASM_HIP_TRY(hipDeviceSynchronize());
+    uint64_t sum = 0;
+    for (unsigned long long c : v) sum += c;
+    *count = sum;
     return LESASM_OK;
 }

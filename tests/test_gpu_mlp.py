@@ -137,3 +137,38 @@ def test_fused_closure_matches_oracle(torch_cuda, net, precision):
     assert 0.2 < use.mean() < 0.8
     mesh.close()
     m.close()
+
+
+def test_fallback_counts_over_many_workgroups(torch_cuda):
+    # the 2.0 M hybrid mesh with the committed network: more chunk workgroups
+    # than fallback counter slots; counts add up over assemblies, the query
+    # resets them, and a zero tolerance counts every element once
+    import json
+    import os
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    case = mg.hybrid_2m_case()
+    data = os.path.join(os.path.dirname(lesasm.__file__), "data")
+    flat = np.load(os.path.join(data, "closure_weights.npy")).astype(np.float32)
+    delta_ref = json.load(open(os.path.join(data, "closure_weights.json")))["delta_ref"]
+    m = lesasm.MLP(flat)
+    mesh = lesasm.Mesh.from_arrays(case.mesh, case.vreman_c)
+    mesh.precision = "fp32"
+    u = mesh.to_internal(torch.from_numpy(case.u).cuda())
+    p = mesh.to_internal(torch.from_numpy(case.p).cuda())
+    lesasm.set_closure(mesh, m, delta_ref, 0.05)
+    assert lesasm.closure_fallbacks(mesh) == 0
+    mesh.assemble_momentum_rhs(u, p, case.nu)
+    one = lesasm.closure_fallbacks(mesh)
+    for _ in range(3):
+        mesh.assemble_momentum_rhs(u, p, case.nu)
+    three = lesasm.closure_fallbacks(mesh)
+    print(f"  fallbacks per assembly {one} of {case.mesh.n_elems}", flush=True)
+    assert 0 < one < case.mesh.n_elems and three == 3 * one
+    assert lesasm.closure_fallbacks(mesh) == 0
+    lesasm.set_closure(mesh, m, delta_ref, 0.0)  # zero tolerance: every element falls back
+    mesh.assemble_momentum_rhs(u, p, case.nu)
+    assert lesasm.closure_fallbacks(mesh) == case.mesh.n_elems
+    lesasm.set_closure(mesh, None)
+    mesh.close()
+    m.close()
