@@ -94,10 +94,6 @@ struct ChunkView {
 };
 
 constexpr uint32_t kOwnedBit = 0x80000000u;
-// Vreman-fallback counts of the learned closure: workgroup b adds to slot
-// b % kFallbackSlots (spread over many addresses: one shared counter made
-// every chunk's closing atomic wait on the others)
-constexpr int kFallbackSlots = 4096;
 
 const short *mlp_packed(const lesasm_mlp *p);
 const float *mlp_bias(const lesasm_mlp *p);

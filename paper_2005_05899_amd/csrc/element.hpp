@@ -428,6 +428,10 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
 //   x[ng][3] | u[nf][3] | p[nf] | acc[nf][3].
 // Learned closure of a launch: packed weights, filter-width reference and
 // the fallback threshold (squared), plus the counters of Vreman fallbacks.
+// Vreman-fallback counts: workgroup b adds to counter b % kFallbackSlots
+// (spread over many addresses: one shared counter made every chunk's closing
+// atomic wait on the others)
+constexpr int kFallbackSlots = 4096;
 struct ClosureView {
     const short *packed;
     const float *bias;
