@@ -534,10 +534,10 @@ def spmv_bytes(nnz: int, n: int) -> int:
 
 
 def cg_bytes_per_iteration(nnz: int, n: int) -> int:
-    """Algorithmic bytes of one Jacobi-CG iteration: the SpMV; the update reads
-    x, p, r, q and the diagonal and writes x, r, z; the direction reads z, p
-    and writes p (8 B per row each)."""
-    return spmv_bytes(nnz, n) + 8 * n * (8 + 3)
+    """Algorithmic bytes of one Jacobi-CG iteration: the SpMV; the residual
+    update reads r, q and the diagonal and writes r, z; the direction step
+    reads x, p, z and writes x, p (8 B per row each)."""
+    return spmv_bytes(nnz, n) + 8 * n * (5 + 5)
 
 
 def run_cg(args):

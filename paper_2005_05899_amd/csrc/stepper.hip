@@ -369,10 +369,10 @@ __global__ void k_sell_fill(const int32_t *__restrict__ src, const double *__res
         sval[i] = src[i] >= 0 ? val[src[i]] : 0.0;
 }
 
-// alpha = rz / pq;  x += alpha p;  r -= alpha q;  z = r / diag;
+// alpha = rz / pq;  r -= alpha q;  z = r / diag  (x is advanced with the old
+// direction by k_cg_direction, which reads p anyway);
 // partial[2b] = block sums of r.z, partial[2b+1] = of r.r
-__global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ x, double *__restrict__ r,
-                                                   double *__restrict__ z, const double *__restrict__ p,
+__global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ r, double *__restrict__ z,
                                                    const double *__restrict__ q, const double *__restrict__ diag,
                                                    const double *__restrict__ scal, int i_rz, int i_pq, int n,
                                                    double *__restrict__ partial) {
@@ -380,7 +380,6 @@ __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ x, doubl
     const double alpha = scal[i_rz] / scal[i_pq];
     double rz = 0.0, rr = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        x[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         const double zi = ri / diag[i];
         r[i] = ri;
@@ -411,11 +410,17 @@ __global__ __launch_bounds__(1024) void k_reduce_strided(const double *__restric
     }
 }
 
-// p = z + (rz_new / rz_old) p
-__global__ __launch_bounds__(256) void k_cg_direction(double *__restrict__ p, const double *__restrict__ z,
-                                                      const double *__restrict__ scal, int i_new, int i_old, int n) {
+// x += (rz_old / pq) p;  p = z + (rz_new / rz_old) p
+__global__ __launch_bounds__(256) void k_cg_direction(double *__restrict__ x, double *__restrict__ p,
+                                                      const double *__restrict__ z, const double *__restrict__ scal,
+                                                      int i_new, int i_old, int i_pq, int n) {
+    const double alpha = scal[i_old] / scal[i_pq];
     const double beta = scal[i_new] / scal[i_old];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double pi = p[i];
+        x[i] += alpha * pi;
+        p[i] = z[i] + beta * pi;
+    }
 }
 
 // y = a0 x0 + a1 x1 + a2 x2 (x1, x2 may be NULL)
@@ -583,12 +588,12 @@ int pressure_solve(lesasm_stepper *st, const double *b_in, double *x, hipStream_
                                    st->q, n, st->partial);
             hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 1, 1,
                                st->scal + S_PQ, st->scal + S_PQ);
-            hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(256), 0, s, x, st->r, st->z, st->pv, st->q,
-                               st->diag, st->scal, i_rz, S_PQ, n, st->partial);
+            hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(256), 0, s, st->r, st->z, st->q, st->diag,
+                               st->scal, i_rz, S_PQ, n, st->partial);
             hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 2, 2,
                                st->scal + i_rzn, st->scal + S_RR);
-            hipLaunchKernelGGL(k_cg_direction, dim3(kCgBlocks), dim3(256), 0, s, st->pv, st->z, st->scal, i_rzn,
-                               i_rz, n);
+            hipLaunchKernelGGL(k_cg_direction, dim3(kCgBlocks), dim3(256), 0, s, x, st->pv, st->z, st->scal, i_rzn,
+                               i_rz, S_PQ, n);
             std::swap(i_rz, i_rzn);
             if (it % st->check_every == 0 || it == st->maxit) {
                 LESASM_HIP_TRY(hipMemcpyAsync(host, st->scal, sizeof(host), hipMemcpyDeviceToHost, s));

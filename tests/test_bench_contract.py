@@ -40,9 +40,9 @@ def test_per_type_bytes_add_up_to_the_mesh():
 
 def test_cg_byte_counts():
     # 10 nonzeros over 3 rows: values and columns 12 B each, p read and q
-    # written once; the iteration adds 11 vector passes of 8 B per row
+    # written once; the iteration adds 10 vector passes of 8 B per row
     assert bench.spmv_bytes(10, 3) == 120 + 48
-    assert bench.cg_bytes_per_iteration(10, 3) == 120 + 48 + 8 * 3 * 11
+    assert bench.cg_bytes_per_iteration(10, 3) == 120 + 48 + 8 * 3 * 10
 
 
 def test_source_hash_ignores_comments_and_layout_but_not_code(tmp_path, monkeypatch):
