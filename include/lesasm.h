@@ -166,6 +166,12 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
                                      as many workgroups as the GPU holds at once, each looping over
                                      chunks (measured slower: it blocks the concurrent type kernels);
                                      N > 1: at most N workgroups (testing) */
+#define LESASM_OPT_GRAPH 9        /* 1 (default): from the second consecutive call with the same u, p,
+                                     rhs, nu and dt (and no profiling, no learned closure, the
+                                     caller's stream not capturing), the assembly is captured once
+                                     into a HIP graph on a stream of the mesh's own and replayed on
+                                     the caller's stream; any option change or new closure drops the
+                                     capture.  0: always launch the kernels one by one */
 
 #define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
 #define LESASM_PREC_FP32 1 /* element contractions in FP32 on coefficients formed in FP64
