@@ -192,7 +192,9 @@ int lesasm_mesh_get_option(const lesasm_mesh *mesh, int option, int64_t *value);
  *   d_rhs  device [n_field_nodes][3], overwritten (zero-filled on the stream
  *          first, then scatter-added).  Must not alias d_u or d_p.
  * Pointers must be 8-byte aligned.  Asynchronous on `stream`; a kernel fault
- * shows at the caller's next synchronisation.
+ * shows at the caller's next synchronisation.  Repeated calls with the same
+ * arguments replay a graph of the assembly captured on the first repeat
+ * (LESASM_OPT_GRAPH); the buffers are read at replay time.
  * Errors: LESASM_E_INVALID_ARG, LESASM_E_STATE (current device differs from
  * the mesh's), LESASM_E_NONFINITE (only with LESASM_OPT_CHECK_FINITE),
  * LESASM_E_HIP (launch failure).                                            */
