@@ -166,12 +166,6 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
                                      as many workgroups as the GPU holds at once, each looping over
                                      chunks (measured slower: it blocks the concurrent type kernels);
                                      N > 1: at most N workgroups (testing) */
-#define LESASM_OPT_GRAPH 9        /* 1 (default): from the second consecutive call with the same u, p,
-                                     rhs, nu and dt (and no profiling, no learned closure, the
-                                     caller's stream not capturing), the assembly is captured once
-                                     into a HIP graph on a stream of the mesh's own and replayed on
-                                     the caller's stream; any option change or new closure drops the
-                                     capture.  0: always launch the kernels one by one */
 
 #define LESASM_PREC_FP64 0 /* whole element computation in FP64 */
 #define LESASM_PREC_FP32 1 /* element contractions in FP32 on coefficients formed in FP64
@@ -192,9 +186,7 @@ int lesasm_mesh_get_option(const lesasm_mesh *mesh, int option, int64_t *value);
  *   d_rhs  device [n_field_nodes][3], overwritten (zero-filled on the stream
  *          first, then scatter-added).  Must not alias d_u or d_p.
  * Pointers must be 8-byte aligned.  Asynchronous on `stream`; a kernel fault
- * shows at the caller's next synchronisation.  Repeated calls with the same
- * arguments replay a graph of the assembly captured on the first repeat
- * (LESASM_OPT_GRAPH); the buffers are read at replay time.
+ * shows at the caller's next synchronisation.
  * Errors: LESASM_E_INVALID_ARG, LESASM_E_STATE (current device differs from
  * the mesh's), LESASM_E_NONFINITE (only with LESASM_OPT_CHECK_FINITE),
  * LESASM_E_HIP (launch failure).                                            */

@@ -9,8 +9,6 @@
 // read-modify-write with a fixed summation order.
 #include <algorithm>
 #include <cmath>
-#include <mutex>
-#include <unordered_map>
 
 #include "element.hpp"
 
@@ -328,104 +326,6 @@ int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, d
     return LESASM_OK;
 }
 
-// Repeated calls with the same buffers and parameters replay a graph of the
-// assembly (fork, element-type kernels, join, gather), captured once on a
-// stream of the library's own and launched on the caller's stream: fewer
-// launch and cross-stream dependency gaps than the eager sequence.  One
-// capture per mesh; an option change or a new closure drops it.
-struct GraphCache {
-    bool enabled = true, failed = false, have = false;
-    int repeats = 0;
-    const double *u = nullptr, *p = nullptr;
-    double *rhs = nullptr;
-    double nu = 0.0, dt = 0.0;
-    hipStream_t cap = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-static std::mutex g_graph_mu;
-static std::unordered_map<const lesasm_mesh *, GraphCache> g_graphs;
-
-void graph_cache_drop(const lesasm_mesh *m, bool erase) {
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    auto it = g_graphs.find(m);
-    if (it == g_graphs.end()) return;
-    GraphCache &g = it->second;
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    g.exec = nullptr;
-    g.have = false;
-    g.repeats = 0;
-    g.failed = false;
-    if (erase) {
-        if (g.cap) (void)hipStreamDestroy(g.cap);
-        g_graphs.erase(it);
-    }
-}
-
-void graph_cache_enable(const lesasm_mesh *m, bool on) {
-    graph_cache_drop(m, false);
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    g_graphs[m].enabled = on;
-}
-
-bool graph_cache_enabled(const lesasm_mesh *m) {
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    auto it = g_graphs.find(m);
-    return it == g_graphs.end() || it->second.enabled;
-}
-
-// Launches the cached graph for this call if there is one (or captures it on
-// the second identical call).  Returns 1 when the assembly was launched, 0
-// when the caller should run it eagerly, < 0 on an error of the launch.
-static int graph_assemble(lesasm_mesh *m, const double *u, const double *p, double nu, double dt, double *rhs,
-                          hipStream_t s, bool increment) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    if (cs != hipStreamCaptureStatusNone) return 0;  // the caller is capturing: record the eager launches
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    GraphCache &g = g_graphs[m];
-    if (!g.enabled || g.failed) return 0;
-    const bool same = g.u == u && g.p == p && g.rhs == rhs && g.nu == nu && g.dt == dt;
-    if (!same) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        g.exec = nullptr;
-        g.have = false;
-        g.u = u, g.p = p, g.rhs = rhs, g.nu = nu, g.dt = dt;
-        g.repeats = 1;
-        return 0;
-    }
-    if (!g.have) {
-        if (++g.repeats < 2) return 0;
-        if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess) {
-            (void)hipGetLastError();
-            g.failed = true;
-            return 0;
-        }
-        if (hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            (void)hipGetLastError();
-            g.failed = true;
-            return 0;
-        }
-        const int rc = assemble_into(m, u, p, nu, dt, rhs, g.cap, increment);
-        hipGraph_t graph = nullptr;
-        const hipError_t e = hipStreamEndCapture(g.cap, &graph);
-        hipError_t ei = hipErrorUnknown;
-        if (rc == LESASM_OK && e == hipSuccess && graph) ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            (void)hipGetLastError();
-            g.exec = nullptr;
-            g.failed = true;  // eager from now on for this mesh
-            return 0;
-        }
-        g.have = true;
-    }
-    LESASM_HIP_TRY(hipGraphLaunch(g.exec, s));
-    return 1;
-}
-
 }  // namespace lesasm
 
 using namespace lesasm;
@@ -459,12 +359,7 @@ extern "C" int lesasm_assemble_momentum_rhs(lesasm_mesh *m, const double *d_u, c
         if (flag) return fail(LESASM_E_NONFINITE, "assemble: u or p holds NaN/Inf");
     }
 
-    const bool increment = m->rhs_mode == LESASM_RHS_INCREMENT;
-    if (!m->profile && !m->mlp) {
-        const int g = graph_assemble(m, d_u, d_p, nu, dt, d_rhs, s, increment);
-        if (g) return g < 0 ? g : LESASM_OK;
-    }
-    return assemble_into(m, d_u, d_p, nu, dt, d_rhs, s, increment);
+    return assemble_into(m, d_u, d_p, nu, dt, d_rhs, s, m->rhs_mode == LESASM_RHS_INCREMENT);
 }
 
 extern "C" int lesasm_mesh_kernel_times(lesasm_mesh *m, double *ms, int64_t *launches, int reset) {

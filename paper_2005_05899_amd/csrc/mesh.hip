@@ -15,11 +15,6 @@
 
 namespace lesasm {
 
-// the assembly's graph cache (assemble.hip)
-void graph_cache_drop(const lesasm_mesh *m, bool erase);
-void graph_cache_enable(const lesasm_mesh *m, bool on);
-bool graph_cache_enabled(const lesasm_mesh *m);
-
 static thread_local std::string g_error;
 
 void set_error(const std::string &msg) { g_error = msg; }
@@ -134,7 +129,6 @@ static void free_mesh(lesasm_mesh *m) {
     const bool have = hipGetDevice(&cur) == hipSuccess;
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
-    graph_cache_drop(m, true);
     for (auto &v : m->pending)
         for (auto &ev : v) {
             (void)hipEventDestroy(ev.first);
@@ -672,11 +666,7 @@ extern "C" int lesasm_mesh_filter_width(const lesasm_mesh *m, double *d_out, voi
 
 extern "C" int lesasm_mesh_set_option(lesasm_mesh *m, int option, int64_t value) {
     if (!m) return fail(LESASM_E_INVALID_ARG, "set_option: mesh is NULL");
-    graph_cache_drop(m, false);
     switch (option) {
-    case LESASM_OPT_GRAPH:
-        graph_cache_enable(m, value != 0);
-        return LESASM_OK;
     case LESASM_OPT_PRECISION:
         if (value != LESASM_PREC_FP64 && value != LESASM_PREC_FP32)
             return fail(LESASM_E_UNSUPPORTED, "set_option: unknown precision");
@@ -732,7 +722,6 @@ extern "C" int lesasm_mesh_get_option(const lesasm_mesh *m, int option, int64_t 
     case LESASM_OPT_CHUNK: *value = m->chunk_elems; return LESASM_OK;
     case LESASM_OPT_CONCURRENT: *value = m->concurrent; return LESASM_OK;
     case LESASM_OPT_PERSISTENT: *value = m->persist; return LESASM_OK;
-    case LESASM_OPT_GRAPH: *value = graph_cache_enabled(m) ? 1 : 0; return LESASM_OK;
     default: return fail(LESASM_E_INVALID_ARG, "get_option: unknown option " + std::to_string(option));
     }
 }
@@ -814,7 +803,6 @@ extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, do
     LESASM_HIP_TRY(hipGetDevice(&cur));
     if (cur != m->device) return fail(LESASM_E_STATE, "set_closure: current device differs from the mesh's device");
     LESASM_HIP_TRY(hipDeviceSynchronize());
-    graph_cache_drop(m, false);
     if (mlp && !m->d_fallbacks) {
         int st = dalloc(m, &m->d_fallbacks, kFallbackSlots);
         if (st) return st;

@@ -20,7 +20,6 @@ TET04, PYR05, PEN06, HEX08 = 4, 5, 6, 8
 MESH_SCATTER_STAGED, MESH_SCATTER_COLOUR, MESH_KEEP_ORDER, MESH_SCATTER_DIRECT, MESH_SCATTER_CHUNK_ATOMIC = 0, 1, 2, 4, 8
 OPT_PRECISION, OPT_RHS_MODE, OPT_CHECK_FINITE, OPT_BLOCK, OPT_PROFILE, OPT_CHUNK, OPT_CONCURRENT = 1, 2, 3, 4, 5, 6, 7
 OPT_PERSISTENT = 8
-OPT_GRAPH = 9
 KERNEL_SLOTS = ("fill", "tet04", "pyr05", "pen06", "hex08", "increment", "gather")
 PREC_FP64, PREC_FP32 = 0, 1
 RHS_RESIDUAL, RHS_INCREMENT = 0, 1

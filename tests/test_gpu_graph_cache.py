@@ -9,7 +9,14 @@ import pytest
 
 from paper_2005_05899_amd import meshgen as mg
 
-pytestmark = pytest.mark.gpu
+# The graph cache is taken out of the library: a run of
+# test_switching_buffers_retires_captures aborted inside the mesh's
+# destruction after several captures and retirements (all its results had
+# matched the eager ones), and no cause was found in the cache's code.  These
+# tests stay, skipped, with the option they exercise.
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="assembly graph cache taken out: an abort in mesh destruction after "
+                                      "repeated captures, cause not found")]
 
 
 @pytest.fixture(scope="module")
@@ -125,3 +132,27 @@ def test_closure_and_profiling_run_eagerly(torch_cuda):
     lesasm.set_closure(mesh, None)
     net.close()
     mesh.close()
+
+
+def test_switching_buffers_retires_captures(torch_cuda):
+    # captures are made and dropped as the output buffer changes, without
+    # waiting for the caller: every result equals the eager one
+    from paper_2005_05899_amd import lesasm
+    torch = torch_cuda
+    c = mg.small_hybrid_case(nx=6, ny=5, seed=24)
+    mesh = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+    ref = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
+    ref.set_option(lesasm.OPT_GRAPH, 0)
+    u = mesh.to_internal(torch.from_numpy(c.u).cuda())
+    p = mesh.to_internal(torch.from_numpy(c.p).cuda())
+    bufs = [torch.empty_like(u), torch.empty_like(u)]
+    outs = []
+    for k, b in enumerate([0, 0, 0, 1, 1, 1, 0, 0, 1, 0, 0, 0]):
+        u.add_(0.001 * k)
+        mesh.assemble_momentum_rhs(u, p, c.nu, out=bufs[b])
+        outs.append((bufs[b].clone(), ref.assemble_momentum_rhs(u, p, c.nu)))
+    torch.cuda.synchronize()
+    for k, (got, want) in enumerate(outs):
+        assert _rel(got, want) <= 1e-13, k
+    mesh.close()
+    ref.close()
