@@ -158,3 +158,96 @@ def test_cg_pins_catch_mutant(name, tmp_path):
     assert src.count(old) == 1, name
     r = _run_cg_pins(src.replace(old, new), tmp_path)
     assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
+
+
+# ---- the learned-closure oracle (Python) -------------------------------------
+
+CLOSURE_SRC = os.path.join(ROOT, "oracle", "closure.py")
+CLOSURE_PINS = "tests/test_oracle_closure.py"
+CLOSURE_MUTANTS = {
+    "fallback_comparison_inverted": ("use[e] = np.linalg.norm(D) ** 2 <= tol * tol * nr * nr",
+                                     "use[e] = np.linalg.norm(D) ** 2 >= tol * tol * nr * nr"),
+    "vreman_stress_sign": ("tau_v = -nut[:, None] * np.stack(", "tau_v = nut[:, None] * np.stack("),
+    "network_stress_drops_width_squared": ("tau_m = (dg ** 2 * g2)[:, None]", "tau_m = (g2)[:, None]"),
+    "network_stress_drops_gradient_norm": ("tau_m = (dg ** 2 * g2)[:, None]", "tau_m = (dg ** 2)[:, None]"),
+    "network_stress_keeps_trace": ("* _mlp.deviatoric(y)", "* y"),
+    "kept_element_drops_vreman_residual": ("RV[e] + D if use[e] else RV[e]", "D if use[e] else RV[e]"),
+    "strain_not_symmetrised": ("S = G + G.transpose(0, 2, 1)", "S = 2.0 * G"),
+    "stress_components_swapped": ("S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]]", "S[:, 0, 1], S[:, 1, 2], S[:, 0, 2]]"),
+    "error_ratio_inverted": ("eps[e] = np.linalg.norm(D) / nr if", "eps[e] = nr / np.linalg.norm(D) if"),
+    "reference_width_for_every_element": ("dg = np.repeat(deltas, ng)", "dg = np.repeat(deltas, ng) * 0 + delta_ref"),
+    "network_sees_transposed_gradient": ("x, g2 = _mlp.features(G, dg, delta_ref)",
+                                         "x, g2 = _mlp.features(G.transpose(0, 2, 1), dg, delta_ref)"),
+}
+
+
+def _run_closure_pins(src_text, tmp_path):
+    mut = tmp_path / "closure_variant.py"
+    mut.write_text(src_text)
+    env = dict(os.environ, LESASM_CLOSURE_ORACLE=str(mut))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", CLOSURE_PINS],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_closure_unmodified_copy_passes(tmp_path):
+    r = _run_closure_pins(open(CLOSURE_SRC).read(), tmp_path)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(CLOSURE_MUTANTS))
+def test_closure_pins_catch_mutant(name, tmp_path):
+    old, new = CLOSURE_MUTANTS[name]
+    src = open(CLOSURE_SRC).read()
+    assert src.count(old) == 1, name
+    r = _run_closure_pins(src.replace(old, new), tmp_path)
+    assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
+
+
+# ---- the closure's training data (Python) -------------------------------------
+
+TRAIN_SRC = os.path.join(ROOT, "paper_2005_05899_amd", "training.py")
+TRAIN_PINS = "tests/test_training_data.py"
+TRAIN_MUTANTS = {
+    "filter_weights": ("f = 0.25 * np.roll(f, 1, axis=ax) + 0.5 * f + 0.25 * np.roll(f, -1, axis=ax)",
+                       "f = 0.3 * np.roll(f, 1, axis=ax) + 0.4 * f + 0.3 * np.roll(f, -1, axis=ax)"),
+    "filter_skips_an_axis": ("    for ax in range(3):\n        f = 0.25", "    for ax in range(2):\n        f = 0.25"),
+    "velocity_restricted_off_grid": ("ub = box_filter(ub)[::2, ::2, ::2]", "ub = box_filter(ub)[::2, 1::2, ::2]"),
+    "products_not_filtered": ("pb = box_filter(pb)[::2, ::2, ::2]", "pb = pb[::2, ::2, ::2]"),
+    "stress_sign": ("tau = pb - np.stack(", "tau = pb + np.stack("),
+    "stress_components_mismatched": (
+        "ub[..., 0] * ub[..., 1], ub[..., 0] * ub[..., 2], ub[..., 1] * ub[..., 2]], axis=-1)\n    return",
+        "ub[..., 0] * ub[..., 2], ub[..., 0] * ub[..., 1], ub[..., 1] * ub[..., 2]], axis=-1)\n    return"),
+    "gradient_axes_reversed": ("np.stack([gxv, gyv, gzv], axis=-1)", "np.stack([gzv, gyv, gxv], axis=-1)"),
+    "gradient_not_scaled_by_spacing": ("f.shape[-1], 3) / h)", "f.shape[-1], 3))"),
+    "interpolation_weight_wrong_axis": ("wx = gx if dx else 1 - gx", "wx = gy if dx else 1 - gy"),
+    "gauss_points_wrong": ("GAUSS_1D = (0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0))",
+                           "GAUSS_1D = (0.5 - 0.5 / math.sqrt(2.0), 0.5 + 0.5 / math.sqrt(2.0))"),
+    "corner_shift_axes_swapped": ("np.roll(f, (-dz, -dy, -dx), axis=(0, 1, 2))",
+                                  "np.roll(f, (-dx, -dy, -dz), axis=(0, 1, 2))"),
+    "target_scaled_by_width_once": ("(tg / (h * h * g2)[:, None])", "(tg / (h * g2)[:, None])"),
+    "width_feature_inverted": ("math.log(h / delta_ref)", "math.log(delta_ref / h)"),
+    "target_keeps_trace": ("        tg = deviatoric(tg)\n", "        tg = tg\n"),
+    "reference_width_of_the_fine_grid": ("delta_ref = length / (n // 2)", "delta_ref = length / n"),
+}
+
+
+def _run_training_pins(src_text, tmp_path):
+    mut = tmp_path / "training_variant.py"
+    mut.write_text(src_text)
+    env = dict(os.environ, LESASM_TRAINING_MODULE=str(mut))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", TRAIN_PINS],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+def test_training_unmodified_copy_passes(tmp_path):
+    r = _run_training_pins(open(TRAIN_SRC).read(), tmp_path)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(TRAIN_MUTANTS))
+def test_training_pins_catch_mutant(name, tmp_path):
+    old, new = TRAIN_MUTANTS[name]
+    src = open(TRAIN_SRC).read()
+    assert src.count(old) == 1, name
+    r = _run_training_pins(src.replace(old, new), tmp_path)
+    assert r.returncode == 1, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
