@@ -187,6 +187,13 @@ int lesasm_mesh_get_option(const lesasm_mesh *mesh, int option, int64_t *value);
  *          first, then scatter-added).  Must not alias d_u or d_p.
  * Pointers must be 8-byte aligned.  Asynchronous on `stream`; a kernel fault
  * shows at the caller's next synchronisation.
+ * Streams: calls on one mesh share its staging rows, events and counters.
+ * When a call comes on another stream than the mesh's previous call (this
+ * entry point, the stepper's, or a batch holding the mesh), the library makes
+ * the new stream wait for the previous call's end, so such calls run one
+ * after another in the order they were made.  Calls made while the stream is
+ * capturing a graph are not ordered this way: replays of a captured call
+ * must be ordered against other calls on the same mesh by the caller.
  * Errors: LESASM_E_INVALID_ARG, LESASM_E_STATE (current device differs from
  * the mesh's), LESASM_E_NONFINITE (only with LESASM_OPT_CHECK_FINITE),
  * LESASM_E_HIP (launch failure).                                            */
@@ -250,6 +257,39 @@ int lesasm_pressure_solve(lesasm_stepper *stepper, const double *d_b, double *d_
 /* CG iterations and relative residual of the last pressure solve. */
 int lesasm_stepper_stats(const lesasm_stepper *stepper, int *cg_iters, double *cg_rel_residual);
 
+/* ---- step graph: one whole time step as a HIP graph ---------------------- */
+/* Algorithm 1's time step (three Runge-Kutta stages with their element
+ * assemblies, b = -(1/dt) D u*, the Jacobi-PCG pressure solve, u^n+1 =
+ * u* - dt M_L^-1 G dp and p^n+1 = p^n + dp; Section 3.2's fractional step),
+ * captured once on `stream` (not the default stream; synchronised first) and
+ * replayed with no host synchronisation.  The CG is captured as exactly
+ * cg_iters iterations (1..100000); its residual is tested on the device after
+ * every iteration and the iterations after the one that met the stepper's
+ * rtol return at once (a replay that needs more than cg_iters ends the step
+ * with the unconverged solve: lesasm_step_graph_stats tells).  The eager step
+ * tests every 16 iterations, so it may run up to 15 more.
+ * Bound at creation to d_u [n_field_nodes][3] and d_p [n_field_nodes]
+ * (internal order, caller-owned, updated in place by every replay) and to the
+ * stepper's work arrays: the stepper and mesh must outlive the graph, and
+ * replays must not overlap other calls on the same stepper or mesh.  Errors:
+ * LESASM_E_INVALID_ARG (NULL, cg_iters out of range, default stream),
+ * LESASM_E_STATE (wrong device, stream already capturing), LESASM_E_OOM,
+ * LESASM_E_HIP (capture or instantiation failed). */
+typedef struct lesasm_step_graph lesasm_step_graph;
+int lesasm_step_graph_create(lesasm_stepper *stepper, double *d_u, double *d_p, int cg_iters,
+                             lesasm_step_graph **out, void *stream);
+
+/* Replay on `stream` (asynchronous).  d_u and d_p must be the pointers given
+ * at creation, else LESASM_E_STATE. */
+int lesasm_step_graph_launch(lesasm_step_graph *graph, double *d_u, double *d_p, void *stream);
+
+/* CG iterations run, relative residual and whether it met rtol, for the last
+ * replay (waits for it).  LESASM_E_STATE before the first replay. */
+int lesasm_step_graph_stats(lesasm_step_graph *graph, int *cg_iters, double *cg_rel_residual, int *converged);
+
+/* Waits for the last replay, then frees the graph. */
+int lesasm_step_graph_destroy(lesasm_step_graph *graph);
+
 /* Copy the assembled Laplacian to host arrays (rowptr[n_field_nodes+1],
  * col[nnz], val[nnz], any of them may be NULL); *nnz receives the count. */
 int lesasm_stepper_laplacian(lesasm_stepper *stepper, int32_t *rowptr, int32_t *col, double *val, int64_t *nnz);
@@ -304,7 +344,9 @@ int lesasm_batch_get_per_type(const lesasm_batch *batch, int *per_type);
  * d_rhs[i] (overwritten).  Same semantics as lesasm_assemble_momentum_rhs per
  * mesh (residual mode); all meshes use the first mesh's precision option.
  * Asynchronous: one small set-up kernel, the persistent element kernel and
- * one gather kernel. */
+ * one gather kernel.  A batch shares its members' staging rows: a call on
+ * another stream than the previous call on the batch or on any member waits
+ * for that call's end (as for lesasm_assemble_momentum_rhs). */
 int lesasm_batch_assemble(lesasm_batch *batch, const double *const *d_u, const double *const *d_p,
                           const double *nu, double *const *d_rhs, void *stream);
 
@@ -323,8 +365,10 @@ int lesasm_batch_tune(lesasm_batch *batch, const double *const *d_u, const doubl
  * k1 = dt M^-1 rhs(u), u2 = u + k1/3, k2 = dt M^-1 rhs(u2), u3 = u + 2 k2/3,
  * k3 = dt M^-1 rhs(u3), u <- u + k1/4 + 3 k3/4.
  *   _graph captures the sequence on `stream` (must not be NULL) into a HIP
- *   graph bound to these pointers; _launch replays it (one host call per
- *   step); _eager runs the same sequence without a graph. */
+ *   graph bound to these pointers (a graph captured before is destroyed
+ *   after its last replay has finished); _launch replays it (one host call
+ *   per step, ordered against other streams as lesasm_batch_assemble);
+ *   _eager runs the same sequence without a graph. */
 int lesasm_batch_rk3_graph(lesasm_batch *batch, double *const *d_u, const double *const *d_p, const double *nu,
                            double dt, void *stream);
 int lesasm_batch_rk3_launch(lesasm_batch *batch, void *stream);
@@ -379,6 +423,10 @@ int lesasm_mesh_set_closure(lesasm_mesh *mesh, const lesasm_mlp *mlp, double del
 /* Number of elements that fell back to Vreman since the last call (resets;
  * synchronises). */
 int lesasm_mesh_closure_fallbacks(lesasm_mesh *mesh, uint64_t *count);
+
+/* The same per element type: counts[4] in the order TET04, PYR05, PEN06,
+ * HEX08 (resets every count; synchronises). */
+int lesasm_mesh_closure_fallbacks_by_type(lesasm_mesh *mesh, uint64_t *counts);
 
 /* ---- wall model (boundary assembly) ------------------------------------ */
 /* Algorithm 1, "Boundary assembly"; Section 3.2 names a law-of-the-wall
@@ -488,6 +536,17 @@ int lesasm_check(void *stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *lesasm_last_error(void);
+
+/* Cap on the device memory this library allocates (meshes, batches,
+ * steppers, networks, step graphs; summed over devices), in bytes; 0 removes
+ * the cap (the default).  An allocation that would pass it fails with
+ * LESASM_E_OOM before any HIP call, and the call that needed it returns that
+ * error with nothing created (for tests of the out-of-memory paths and for
+ * budgeting).  Caller-supplied buffers are not counted.  Thread-safe. */
+int lesasm_set_memory_cap(uint64_t bytes);
+
+/* Device bytes the library holds now (all devices).  Thread-safe. */
+int lesasm_memory_in_use(uint64_t *bytes);
 
 int lesasm_version(void);
 

@@ -6,7 +6,7 @@ with the GPU library.  ``lesasm_oracle.c`` holds the arithmetic; this module
 compiles it with gcc and wraps it with ctypes.
 """
 from .oracle import (TERM_ALL, TERM_CONV, TERM_LITERAL, TERM_PRES, TERM_SGS, TERM_VISC,  # noqa: F401
-                     assemble, build, divergence, element_laplacian, element_residual, element_stress_residual,
+                     assemble, assemble_threads, build, divergence, element_laplacian, element_residual, element_stress_residual,
                      element_volume,
                      filter_width, friction_velocity, gauss, load, lumped_mass, ngauss, nnode, shape, vreman,
                      wall_assemble, wall_law)

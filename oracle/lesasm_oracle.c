@@ -36,7 +36,9 @@
  * invariants, exact rational integration or brute force (see tests/).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define ORACLE_MAX_NODE 8
@@ -439,6 +441,60 @@ int oracle_assemble(int64_t n_nodes, const double *coords, int64_t n_elems, cons
     }
     return 0;
 }
+
+/* Timing leg of the benchmark's CPU baseline: the same element loop as
+ * oracle_assemble, the elements split into nthreads contiguous ranges run by
+ * OpenMP threads, each thread summing into a private right-hand side; the
+ * private arrays are then added node by node in thread order (deterministic).
+ * The result equals oracle_assemble's up to the order of the nodal sums.
+ * Needs 3 * n_field * nthreads doubles of host memory; returns -3 if they
+ * cannot be allocated. */
+int oracle_assemble_threads(int64_t n_nodes, const double *coords, int64_t n_elems, const uint8_t *types,
+                            const int64_t *offs, const int32_t *conn, const int32_t *field_node, int64_t n_field,
+                            const double *u, const double *p, double nu, double c, int terms, int nthreads,
+                            double *rhs)
+{
+    if (nthreads < 1) nthreads = 1;
+    const int64_t len = 3 * n_field;
+    double *priv = (double *)calloc((size_t)nthreads * (size_t)(len > 0 ? len : 1), sizeof(double));
+    if (!priv) return -3;
+    int status = 0;
+    long long bad = -1;
+    g_bad_element = -1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+        const int64_t e0 = n_elems * t / nt, e1 = n_elems * (t + 1) / nt;
+        double *mine = priv + (size_t)t * (size_t)len;
+        double x[3 * ORACLE_MAX_NODE], ue[3 * ORACLE_MAX_NODE], pe[ORACLE_MAX_NODE], R[3 * ORACLE_MAX_NODE];
+        int64_t fid[ORACLE_MAX_NODE];
+        for (int64_t e = e0; e < e1; ++e) {
+            const int n = gather(e, n_nodes, coords, types, offs, conn, field_node, n_field, u, p, x, ue, pe, fid);
+            const int st = n < 0 ? -1 : oracle_element_residual(types[e], x, ue, p ? pe : NULL, nu, c, terms, R,
+                                                                 NULL, NULL);
+            if (st) {
+#pragma omp critical
+                if (bad < 0 || e < bad) { bad = e; status = st; }
+                break;
+            }
+            for (int a = 0; a < n; ++a)
+                for (int i = 0; i < 3; ++i) mine[3 * fid[a] + i] += R[3 * a + i];
+        }
+#pragma omp barrier
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < len; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < nt; ++q) s += priv[(size_t)q * (size_t)len + k];
+            rhs[k] = s;
+        }
+    }
+    free(priv);
+    if (status) { g_bad_element = bad; return status; }
+    return 0;
+}
+
+/* Threads oracle_assemble_threads would use with nthreads = 0 (the OpenMP default). */
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* Row-sum lumped mass M[f] = sum_e sum_g w_g det J_g N_a(xi_g), M[n_field]. */
 int oracle_lumped_mass(int64_t n_nodes, const double *coords, int64_t n_elems, const uint8_t *types,

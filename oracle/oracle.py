@@ -23,7 +23,7 @@ def build(src: str = SRC, out: str = LIB) -> str:
     """Compile the oracle with plain gcc -O2 (no fast-math, no FMA contraction)."""
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
                            "-Wall", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
@@ -53,6 +53,7 @@ def load():
         lib.oracle_element_volume.argtypes = [i32, P, P]
         lib.oracle_element_residual.argtypes = [i32, P, P, P, f64, f64, i32, P, P, P]
         lib.oracle_assemble.argtypes = [i64, P, i64, P, P, P, P, i64, P, P, f64, f64, i32, P]
+        lib.oracle_assemble_threads.argtypes = [i64, P, i64, P, P, P, P, i64, P, P, f64, f64, i32, i32, P]
         lib.oracle_lumped_mass.argtypes = [i64, P, i64, P, P, P, P, i64, P]
         lib.oracle_filter_width.argtypes = [i64, P, i64, P, P, P, P]
         lib.oracle_element_laplacian.argtypes = [i32, P, P]
@@ -156,6 +157,20 @@ def assemble(mesh, u, p=None, nu=0.0, c=0.1, terms=TERM_ALL) -> np.ndarray:
     rhs = np.zeros((nf, 3))
     _check(load().oracle_assemble(len(coords), _p(coords), len(types), _p(types), _p(offs), _p(conn), _p(fn), nf,
                                   _p(u), _p(p), float(nu), float(c), int(terms), _p(rhs)))
+    return rhs
+
+
+def assemble_threads(mesh, u, p=None, nu=0.0, c=0.1, threads=1, terms=TERM_ALL) -> np.ndarray:
+    """The same assembly split over `threads` OpenMP threads (contiguous element
+    ranges, private right-hand sides summed in thread order): the timing leg of
+    the benchmark's CPU baseline.  Equal to assemble() up to the order of the
+    nodal sums."""
+    coords, types, offs, conn, fn, nf = _mesh_args(mesh)
+    u = _f64(u, (nf, 3))
+    p = None if p is None else _f64(p, (nf,))
+    rhs = np.zeros((nf, 3))
+    _check(load().oracle_assemble_threads(len(coords), _p(coords), len(types), _p(types), _p(offs), _p(conn), _p(fn),
+                                          nf, _p(u), _p(p), float(nu), float(c), int(terms), int(threads), _p(rhs)))
     return rhs
 
 

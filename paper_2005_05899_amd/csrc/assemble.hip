@@ -255,6 +255,12 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
         }
         ++used;
         ProfileScope ps(m, LESASM_KERNEL_TET04 + k, sk);
+        ClosureView clk{};
+        if (cl) {  // fallback counters of this category
+            clk = clv;
+            clk.fallbacks = m->d_fallbacks + (size_t)k * kFallbackSlots;
+            cl = &clk;
+        }
         const bool periodic = c.d_lf != c.d_lg;
         const bool f32 = m->precision == LESASM_PREC_FP32;
         if (staged) {
@@ -311,11 +317,14 @@ int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, d
                   bool increment) {
     if (m->n_field == 0) return LESASM_OK;
     const size_t n3 = 3 * (size_t)m->n_field;
+    bool capturing = false;
+    int st = mesh_order_begin(m, s, &capturing);
+    if (st) return st;
     if (!mesh_is_staged(m)) {  // the staged scatter writes every node exactly once
         ProfileScope ps(m, LESASM_KERNEL_FILL, s);
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n3, 256)), dim3(256), 0, s, rhs, n3, 0.0);
     }
-    int st = launch_assembly(m, u, p, nu, rhs, s);
+    st = launch_assembly(m, u, p, nu, rhs, s);
     if (st) return st;
     if (increment) {
         ProfileScope ps(m, LESASM_KERNEL_INCREMENT, s);
@@ -323,7 +332,7 @@ int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, d
                            (size_t)m->n_field);
     }
     LESASM_HIP_TRY(hipGetLastError());
-    return LESASM_OK;
+    return mesh_order_end(m, s, capturing);
 }
 
 }  // namespace lesasm

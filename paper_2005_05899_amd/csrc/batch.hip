@@ -207,6 +207,10 @@ struct lesasm_batch {
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_tune_ms = 0.0;
+    // end of the last assembly or replay (cross-stream ordering with the
+    // member meshes, and the wait before an executable graph is destroyed)
+    hipEvent_t ev_done = nullptr;
+    bool done_recorded = false;
 };
 
 namespace {
@@ -215,11 +219,8 @@ template <class T> int balloc(lesasm_batch *b, T **p, size_t n) {
     *p = nullptr;
     if (!n) return LESASM_OK;
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, n * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(LESASM_E_OOM, "batch: hipMalloc failed");
-    }
+    int st = device_alloc(&q, n * sizeof(T), "batch");
+    if (st) return st;
     b->allocs.push_back(q);
     *p = (T *)q;
     return LESASM_OK;
@@ -229,7 +230,7 @@ template <class T> void bfree(lesasm_batch *b, T *&p) {
     if (!p) return;
     auto it = std::find(b->allocs.begin(), b->allocs.end(), (void *)p);
     if (it != b->allocs.end()) {
-        (void)hipFree(p);
+        device_free(p);
         b->allocs.erase(it);
     }
     p = nullptr;
@@ -243,12 +244,53 @@ void batch_free(lesasm_batch *b) {
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 3; ++i)  // (the side streams are the device's)
         if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
-        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    if (b->ev_done) {
+        for (lesasm_mesh *m : b->meshes)  // the members outlive the batch
+            if (m->order_ev == b->ev_done) m->order_ev = nullptr;
+        (void)hipEventDestroy(b->ev_done);
     }
-    for (void *p : b->allocs) (void)hipFree(p);
+    for (void *p : b->allocs) device_free(p);
     delete b;
+}
+
+// Cross-stream ordering of a batch call with earlier calls on its member
+// meshes (which share their staging rows with the batch) and on the batch
+// itself; nothing while s is capturing.
+int batch_order_begin(lesasm_batch *b, hipStream_t s, bool *capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    LESASM_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    *capturing = cs != hipStreamCaptureStatusNone;
+    if (*capturing) return LESASM_OK;
+    hipEvent_t last = nullptr;
+    for (lesasm_mesh *m : b->meshes)
+        if (m->order_ev && m->order_stream != s && m->order_ev != last) {
+            LESASM_HIP_TRY(hipStreamWaitEvent(s, m->order_ev, 0));
+            last = m->order_ev;
+        }
+    return LESASM_OK;
+}
+
+int batch_order_end(lesasm_batch *b, hipStream_t s, bool capturing) {
+    if (capturing) return LESASM_OK;
+    LESASM_HIP_TRY(hipEventRecord(b->ev_done, s));
+    b->done_recorded = true;
+    for (lesasm_mesh *m : b->meshes) {
+        m->order_ev = b->ev_done;
+        m->order_stream = s;
+    }
+    return LESASM_OK;
+}
+
+// Destroys the captured Runge-Kutta graph after its last replay has finished.
+void drop_graph(lesasm_batch *b) {
+    if (!b->graph_exec && !b->graph) return;
+    if (b->done_recorded) (void)hipEventSynchronize(b->ev_done);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
 }
 
 // Work items ordered by the queue policy.  Cost of a chunk = elements x Gauss
@@ -368,12 +410,7 @@ int rebuild(lesasm_batch *b) {
     int st;
     if ((st = build_tables(b))) return st;
     if ((st = build_work(b))) return st;
-    if (b->graph_exec) {  // chunk arrays moved: an instantiated graph is stale
-        (void)hipGraphExecDestroy(b->graph_exec);
-        (void)hipGraphDestroy(b->graph);
-        b->graph_exec = nullptr;
-        b->graph = nullptr;
-    }
+    drop_graph(b);  // chunk arrays moved: an instantiated graph is stale
     return LESASM_OK;
 }
 
@@ -491,10 +528,9 @@ extern "C" int lesasm_batch_create(lesasm_mesh *const *meshes, int n, lesasm_bat
     LESASM_HIP_TRY(hipEventCreate(&b->ev0));
     LESASM_HIP_TRY(hipEventCreate(&b->ev1));
     LESASM_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-    for (int i = 0; i < 3; ++i) {
-        LESASM_HIP_TRY(hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming));
-        LESASM_HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
-    }
+    LESASM_HIP_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+    for (int i = 0; i < 3; ++i) LESASM_HIP_TRY(hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming));
+    if ((st = device_side_streams(dev, b->side))) return st;
     b->chunk = meshes[0]->chunk_elems;
     if ((st = build_tables(b)) || (st = build_work(b))) return st;
     guard.p = nullptr;
@@ -551,7 +587,11 @@ extern "C" int lesasm_batch_assemble(lesasm_batch *b, const double *const *d_u, 
     int st = make_call(b, d_u, d_p, nu, d_rhs, call);
     if (st) return st;
     const bool fp32 = b->meshes[0]->precision == LESASM_PREC_FP32;
-    return batch_launch(b, call, d_p != nullptr, fp32, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    bool capturing = false;
+    if ((st = batch_order_begin(b, s, &capturing))) return st;
+    if ((st = batch_launch(b, call, d_p != nullptr, fp32, s))) return st;
+    return batch_order_end(b, s, capturing);
 }
 
 // Autotuner: times the batched assembly for every chunk length in `chunks`
@@ -566,6 +606,7 @@ extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, cons
     for (lesasm_mesh *m : b->meshes)
         for (int k = 0; k < kNumCat; ++k) sig << "_" << m->cat[k].n;
     const std::string key = sig.str();
+    LESASM_HIP_TRY(hipDeviceSynchronize());  // earlier calls on any stream end first (the tuner runs on stream 0)
     if (cache_path && *cache_path) {
         std::ifstream in(cache_path);
         std::string k;
@@ -694,12 +735,7 @@ extern "C" int lesasm_batch_rk3_graph(lesasm_batch *b, double *const *d_u, const
             (st = balloc(b, &b->us, 3 * (size_t)b->total_nodes)))
             return st;
     }
-    if (b->graph_exec) {
-        (void)hipGraphExecDestroy(b->graph_exec);
-        (void)hipGraphDestroy(b->graph);
-        b->graph_exec = nullptr;
-        b->graph = nullptr;
-    }
+    drop_graph(b);  // waits for the previous graph's last replay
     LESASM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     st = rk3_record(b, d_u, d_p, nu, dt, s);
     hipGraph_t g = nullptr;
@@ -716,8 +752,12 @@ extern "C" int lesasm_batch_rk3_graph(lesasm_batch *b, double *const *d_u, const
 
 extern "C" int lesasm_batch_rk3_launch(lesasm_batch *b, void *stream) {
     if (!b || !b->graph_exec) return fail(LESASM_E_STATE, "batch_rk3_launch: no captured step");
-    LESASM_HIP_TRY(hipGraphLaunch(b->graph_exec, (hipStream_t)stream));
-    return LESASM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    bool capturing = false;
+    int st = batch_order_begin(b, s, &capturing);
+    if (st) return st;
+    LESASM_HIP_TRY(hipGraphLaunch(b->graph_exec, s));
+    return batch_order_end(b, s, capturing);
 }
 
 extern "C" int lesasm_batch_rk3_eager(lesasm_batch *b, double *const *d_u, const double *const *d_p,
@@ -729,5 +769,9 @@ extern "C" int lesasm_batch_rk3_eager(lesasm_batch *b, double *const *d_u, const
             (st = balloc(b, &b->us, 3 * (size_t)b->total_nodes)))
             return st;
     }
-    return rk3_record(b, d_u, d_p, nu, dt, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    bool capturing = false;
+    if ((st = batch_order_begin(b, s, &capturing))) return st;
+    if ((st = rk3_record(b, d_u, d_p, nu, dt, s))) return st;
+    return batch_order_end(b, s, capturing);
 }

@@ -98,6 +98,24 @@ constexpr uint32_t kOwnedBit = 0x80000000u;
 const short *mlp_packed(const lesasm_mlp *p);
 const float *mlp_bias(const lesasm_mlp *p);
 
+// Device memory of the library: every allocation goes through these, which
+// count the bytes held and refuse, with LESASM_E_OOM and before any HIP call,
+// an allocation that would pass the cap of lesasm_set_memory_cap.
+int device_alloc(void **p, size_t bytes, const char *what);
+void device_free(void *p);
+
+// Three side streams per device, shared by every mesh and batch on it
+// (created on first use, kept until the process ends).
+int device_side_streams(int device, hipStream_t out[3]);
+
+// Ordering of calls that share a mesh's mutable state (staging rows, fork and
+// join events, fallback counters) across streams: mesh_order_begin makes s
+// wait for the previous call's last work when that ran on another stream;
+// mesh_order_end records this call's end.  Neither does anything while s is
+// capturing a graph (the graph's replays are ordered by their stream).
+int mesh_order_begin(lesasm_mesh *m, hipStream_t s, bool *capturing);
+int mesh_order_end(lesasm_mesh *m, hipStream_t s, bool capturing);
+
 // Shared between translation units.
 int grid_for(size_t n, int block);
 int assemble_into(lesasm_mesh *m, const double *u, const double *p, double nu, double dt, double *rhs, hipStream_t s,
@@ -157,6 +175,12 @@ struct lesasm_mesh {
     int chunk_max_nodes = 800;              // node cap of a chunk (LDS budget)
     unsigned long long *d_fallbacks = nullptr;  // kFallbackSlots counters
     hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+    // cross-stream ordering: the event marking the end of the last call that
+    // used this mesh's state (the mesh's own ev_done, or its batch's), and the
+    // stream it was recorded on
+    hipEvent_t ev_done = nullptr;
+    hipEvent_t order_ev = nullptr;
+    hipStream_t order_stream = nullptr;
     // wall model (boundary assembly): per wall face, the nodes of the face and
     // of the volume element it bounds, in internal numbering
     std::vector<int32_t> h_gint, h_fint;  // user geometry node -> internal geometry / field node

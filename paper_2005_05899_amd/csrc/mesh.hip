@@ -6,6 +6,8 @@
 // filter width Delta_e = V_e^(1/3) and the row-sum lumped mass (the
 // mass-matrix listing of Section 3.4.3, summed over each row).
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 #include <climits>
 #include <cstring>
 #include <memory>
@@ -89,17 +91,84 @@ __global__ void k_permute(const double *__restrict__ in, double *__restrict__ ou
 
 int grid_for(size_t n, int block);
 
+// ---- device memory accounting -------------------------------------------------
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void *, size_t> g_mem_sizes;
+uint64_t g_mem_in_use = 0, g_mem_cap = 0;  // cap 0: none
+std::mutex g_side_mu;
+constexpr int kMaxDevices = 64;
+hipStream_t g_side[kMaxDevices][3];
+}  // namespace
+
+int device_alloc(void **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    if (bytes == 0) return LESASM_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        if (g_mem_cap && g_mem_in_use + bytes > g_mem_cap)
+            return fail(LESASM_E_OOM, std::string(what) + ": allocation of " + std::to_string(bytes) +
+                                          " bytes would pass the memory cap (" + std::to_string(g_mem_cap) +
+                                          " bytes, " + std::to_string(g_mem_in_use) + " in use)");
+        g_mem_in_use += bytes;  // reserved before the allocation
+    }
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        g_mem_in_use -= bytes;
+        return fail(LESASM_E_OOM, std::string(what) + ": hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                      hipGetErrorString(e));
+    }
+    g_mem_sizes[q] = bytes;
+    *p = q;
+    return LESASM_OK;
+}
+
+void device_free(void *p) {
+    if (!p) return;
+    (void)hipFree(p);
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_mem_sizes.find(p);
+    if (it != g_mem_sizes.end()) {
+        g_mem_in_use -= it->second;
+        g_mem_sizes.erase(it);
+    }
+}
+
+int device_side_streams(int device, hipStream_t out[3]) {
+    if (device < 0 || device >= kMaxDevices) return fail(LESASM_E_UNSUPPORTED, "side streams: device id too large");
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    for (int i = 0; i < 3; ++i)
+        if (!g_side[device][i]) LESASM_HIP_TRY(hipStreamCreateWithFlags(&g_side[device][i], hipStreamNonBlocking));
+    for (int i = 0; i < 3; ++i) out[i] = g_side[device][i];
+    return LESASM_OK;
+}
+
+int mesh_order_begin(lesasm_mesh *m, hipStream_t s, bool *capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    LESASM_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    *capturing = cs != hipStreamCaptureStatusNone;
+    if (!*capturing && m->order_ev && m->order_stream != s) LESASM_HIP_TRY(hipStreamWaitEvent(s, m->order_ev, 0));
+    return LESASM_OK;
+}
+
+int mesh_order_end(lesasm_mesh *m, hipStream_t s, bool capturing) {
+    if (capturing) return LESASM_OK;
+    LESASM_HIP_TRY(hipEventRecord(m->ev_done, s));
+    m->order_ev = m->ev_done;
+    m->order_stream = s;
+    return LESASM_OK;
+}
+
 // ---- host helpers ------------------------------------------------------------
 template <class T> static int dalloc(lesasm_mesh *m, T **p, size_t n) {
     *p = nullptr;
     if (n == 0) return LESASM_OK;
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, n * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(LESASM_E_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed: " +
-                                      hipGetErrorString(e));
-    }
+    int st = device_alloc(&q, n * sizeof(T), "mesh");
+    if (st) return st;
     m->allocs.push_back(q);
     m->bytes += n * sizeof(T);
     *p = (T *)q;
@@ -134,12 +203,11 @@ static void free_mesh(lesasm_mesh *m) {
             (void)hipEventDestroy(ev.first);
             (void)hipEventDestroy(ev.second);
         }
-    for (int i = 0; i < 3; ++i) {
-        if (m->side[i]) (void)hipStreamDestroy(m->side[i]);
+    for (int i = 0; i < 3; ++i)  // (the side streams are the device's, not the mesh's)
         if (m->ev_join[i]) (void)hipEventDestroy(m->ev_join[i]);
-    }
     if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
-    for (void *p : m->allocs) (void)hipFree(p);
+    if (m->ev_done) (void)hipEventDestroy(m->ev_done);
+    for (void *p : m->allocs) device_free(p);
     if (have) (void)hipSetDevice(cur);
     delete m;
 }
@@ -182,7 +250,7 @@ template <class T> static void dfree(lesasm_mesh *m, T *&p) {
     if (!p) return;
     auto it = std::find(m->allocs.begin(), m->allocs.end(), (void *)p);
     if (it != m->allocs.end()) {
-        (void)hipFree(p);
+        device_free(p);
         m->allocs.erase(it);
     }
     p = nullptr;
@@ -272,6 +340,9 @@ static int build_chunks(lesasm_mesh *m, int k) {
             fslot[f] = -1;
         }
         c.lds_doubles = std::max(c.lds_doubles, (int)(3 * gl.size() + 7 * fl.size()));
+        // chunk node lists are indexed with int32 offsets on the GPU
+        if (gnodes.size() >= (size_t)INT32_MAX || fnodes.size() >= (size_t)INT32_MAX)
+            return fail(LESASM_E_UNSUPPORTED, "mesh_create: chunk node lists of one element type exceed 2^31 entries");
         eoff.push_back((int32_t)e);
         goff.push_back((int32_t)gnodes.size());
         foff.push_back((int32_t)fnodes.size());
@@ -362,11 +433,10 @@ static int build_scatter(lesasm_mesh *m) {
         if ((st = build_chunks(m, k))) return st;
     if (is_staged(m) && (st = build_staging(m))) return st;
     if (!m->side[0]) {
-        for (int i = 0; i < 3; ++i) {
-            LESASM_HIP_TRY(hipStreamCreateWithFlags(&m->side[i], hipStreamNonBlocking));
-            LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming));
-        }
+        if ((st = device_side_streams(m->device, m->side))) return st;
+        for (int i = 0; i < 3; ++i) LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming));
         LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+        LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming));
     }
     return LESASM_OK;
 }
@@ -376,6 +446,19 @@ static int build_scatter(lesasm_mesh *m) {
 using namespace lesasm;
 
 extern "C" const char *lesasm_last_error(void) { return g_error.c_str(); }
+
+extern "C" int lesasm_set_memory_cap(uint64_t bytes) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_cap = bytes;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_memory_in_use(uint64_t *bytes) {
+    if (!bytes) return fail(LESASM_E_INVALID_ARG, "memory_in_use: NULL argument");
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    *bytes = g_mem_in_use;
+    return LESASM_OK;
+}
 
 extern "C" int lesasm_version(void) { return LESASM_VERSION; }
 
@@ -803,10 +886,10 @@ extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, do
     LESASM_HIP_TRY(hipGetDevice(&cur));
     if (cur != m->device) return fail(LESASM_E_STATE, "set_closure: current device differs from the mesh's device");
     LESASM_HIP_TRY(hipDeviceSynchronize());
-    if (mlp && !m->d_fallbacks) {
-        int st = dalloc(m, &m->d_fallbacks, kFallbackSlots);
+    if (mlp && !m->d_fallbacks) {  // kFallbackSlots counters per category
+        int st = dalloc(m, &m->d_fallbacks, (size_t)kNumCat * kFallbackSlots);
         if (st) return st;
-        LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long) * kFallbackSlots));
+        LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long) * kNumCat * kFallbackSlots));
     }
     m->mlp = mlp;
     m->delta_ref = mlp ? delta_ref : 1.0;
@@ -819,17 +902,25 @@ extern "C" int lesasm_mesh_set_closure(lesasm_mesh *m, const lesasm_mlp *mlp, do
     return LESASM_OK;
 }
 
-extern "C" int lesasm_mesh_closure_fallbacks(lesasm_mesh *m, uint64_t *count) {
-    if (!m || !count) return fail(LESASM_E_INVALID_ARG, "closure_fallbacks: NULL argument");
-    *count = 0;
+extern "C" int lesasm_mesh_closure_fallbacks_by_type(lesasm_mesh *m, uint64_t *counts) {
+    if (!m || !counts) return fail(LESASM_E_INVALID_ARG, "closure_fallbacks: NULL argument");
+    for (int k = 0; k < kNumCat; ++k) counts[k] = 0;
     if (!m->d_fallbacks) return LESASM_OK;
-    std::vector<unsigned long long> v(kFallbackSlots);
+    std::vector<unsigned long long> v((size_t)kNumCat * kFallbackSlots);
     LESASM_HIP_TRY(hipDeviceSynchronize());
     LESASM_HIP_TRY(hipMemcpy(v.data(), m->d_fallbacks, sizeof(unsigned long long) * v.size(), hipMemcpyDeviceToHost));
     LESASM_HIP_TRY(hipMemset(m->d_fallbacks, 0, sizeof(unsigned long long) * v.size()));
     LESASM_HIP_TRY(hipDeviceSynchronize());
-    uint64_t sum = 0;
-    for (unsigned long long c : v) sum += c;
-    *count = sum;
+    for (int k = 0; k < kNumCat; ++k)
+        for (int i = 0; i < kFallbackSlots; ++i) counts[k] += v[(size_t)k * kFallbackSlots + i];
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mesh_closure_fallbacks(lesasm_mesh *m, uint64_t *count) {
+    if (!count) return fail(LESASM_E_INVALID_ARG, "closure_fallbacks: NULL argument");
+    uint64_t c[kNumCat];
+    const int st = lesasm_mesh_closure_fallbacks_by_type(m, c);
+    if (st) return st;
+    *count = c[0] + c[1] + c[2] + c[3];
     return LESASM_OK;
 }

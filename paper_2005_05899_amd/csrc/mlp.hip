@@ -233,8 +233,7 @@ struct lesasm_mlp {
 };
 
 static void mlp_free_work(lesasm_mlp *p) {
-    for (float *q : {p->H1, p->H2, p->DY, p->DA1, p->DA2, p->loss})
-        if (q) (void)hipFree(q);
+    for (float *q : {p->H1, p->H2, p->DY, p->DA1, p->DA2, p->loss}) device_free(q);
     p->H1 = p->H2 = p->DY = p->DA1 = p->DA2 = p->loss = nullptr;
     p->cap = 0;
 }
@@ -244,7 +243,7 @@ static void mlp_free(lesasm_mlp *p) {
     (void)hipDeviceSynchronize();
     mlp_free_work(p);
     for (void *q : {(void *)p->params, (void *)p->m, (void *)p->v, (void *)p->grad, (void *)p->packed, (void *)p->bias})
-        if (q) (void)hipFree(q);
+        device_free(q);
     delete p;
 }
 
@@ -266,10 +265,10 @@ static int mlp_work(lesasm_mlp *p, int n) {
     for (auto pr : {std::make_pair(&p->H1, N * kMlpH), std::make_pair(&p->H2, N * kMlpH),
                     std::make_pair(&p->DY, N * kMlpOut), std::make_pair(&p->DA1, N * kMlpH),
                     std::make_pair(&p->DA2, N * kMlpH), std::make_pair(&p->loss, N)}) {
-        if (hipMalloc((void **)pr.first, pr.second * sizeof(float)) != hipSuccess) {
-            (void)hipGetLastError();
+        const int st = device_alloc((void **)pr.first, pr.second * sizeof(float), "mlp work arrays");
+        if (st) {
             mlp_free_work(p);
-            return fail(LESASM_E_OOM, "mlp: work arrays");
+            return st;
         }
     }
     p->cap = n;
@@ -291,10 +290,8 @@ extern "C" int lesasm_mlp_create(const float *params, lesasm_mlp **out) {
                     std::make_pair((void **)&p->grad, sizeof(float) * kMlpParams),
                     std::make_pair((void **)&p->packed, sizeof(short) * kMlpPackedShorts),
                     std::make_pair((void **)&p->bias, sizeof(float) * (2 * kMlpH + 8))}) {
-        if (hipMalloc(pr.first, pr.second) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(LESASM_E_OOM, "mlp_create: hipMalloc failed");
-        }
+        const int st = device_alloc(pr.first, pr.second, "mlp_create");
+        if (st) return st;
     }
     LESASM_HIP_TRY(hipMemcpy(p->params, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     LESASM_HIP_TRY(hipMemset(p->m, 0, sizeof(float) * kMlpParams));

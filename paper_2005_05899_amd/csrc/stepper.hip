@@ -249,8 +249,14 @@ __global__ void k_reduce_final(const double *__restrict__ partial, int nb, doubl
 #define LESASM_CG_UNROLL 4
 #endif
 constexpr int kCgBlocks = LESASM_CG_BLOCKS;
+constexpr int kMaxCapturedCg = 100000;  // CG iterations a step graph may hold
 constexpr int kLanesPerRow = LESASM_CG_LANES;
 constexpr int kRowUnroll = LESASM_CG_UNROLL;
+
+// Captured CG iterations (the step graph): iteration `it` runs only while
+// it <= *state, where *state is the iteration that met the tolerance
+// (INT32_MAX until then).  Eager solves pass state = NULL.
+__device__ __forceinline__ bool cg_skip(const int *state, int it) { return state && it > *state; }
 
 // Fixed-order sum of one value per thread of a 256-thread block into out[0].
 __device__ __forceinline__ void block_sum_256(double v, double *sh, double *out) {
@@ -269,7 +275,9 @@ __device__ __forceinline__ void block_sum_256(double v, double *sh, double *out)
 // partial[b] = block sums of p.q.  Each lane adds its entries in row order.
 __global__ __launch_bounds__(256) void k_spmv_dot(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                                   const double *__restrict__ val, const double *__restrict__ p,
-                                                  double *__restrict__ q, int n, double *__restrict__ partial) {
+                                                  double *__restrict__ q, int n, double *__restrict__ partial,
+                                                  const int *state = nullptr, int it = 0) {
+    if (cg_skip(state, it)) return;
     __shared__ double sh[256];
     const int lane = threadIdx.x % kLanesPerRow;
     const int rows_per_block = 256 / kLanesPerRow;
@@ -330,7 +338,9 @@ __global__ __launch_bounds__(256) void k_spmv_sell_dot(const int32_t *__restrict
                                                        const int32_t *__restrict__ scol,
                                                        const double *__restrict__ sval, const double *__restrict__ p,
                                                        double *__restrict__ q, int n, int nslices,
-                                                       double *__restrict__ partial) {
+                                                       double *__restrict__ partial, const int *state = nullptr,
+                                                       int it = 0) {
+    if (cg_skip(state, it)) return;
     __shared__ double sh[256];
     const int lane = threadIdx.x % kSlice, wave = threadIdx.x / kSlice;
     const int waves = 256 / kSlice;
@@ -375,7 +385,9 @@ __global__ void k_sell_fill(const int32_t *__restrict__ src, const double *__res
 __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ r, double *__restrict__ z,
                                                    const double *__restrict__ q, const double *__restrict__ diag,
                                                    const double *__restrict__ scal, int i_rz, int i_pq, int n,
-                                                   double *__restrict__ partial) {
+                                                   double *__restrict__ partial, const int *state = nullptr,
+                                                   int it = 0) {
+    if (cg_skip(state, it)) return;
     __shared__ double sh[256];
     const double alpha = scal[i_rz] / scal[i_pq];
     double rz = 0.0, rr = 0.0;
@@ -392,9 +404,13 @@ __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ r, doubl
 }
 
 // out[j] = fixed-order sum of partial[stride * b + j] over b < nb, for j < m
-// (one 1024-thread block).
+// (one 1024-thread block).  In a captured CG with conv set, iteration `it`
+// that brings out1 (r.r) to at most tol2 * (*bb) records itself in *state.
 __global__ __launch_bounds__(1024) void k_reduce_strided(const double *__restrict__ partial, int nb, int stride,
-                                                         int m, double *__restrict__ out0, double *__restrict__ out1) {
+                                                         int m, double *__restrict__ out0, double *__restrict__ out1,
+                                                         int *state = nullptr, int it = 0, bool conv = false,
+                                                         const double *bb = nullptr, double tol2 = 0.0) {
+    if (cg_skip(state, it)) return;
     __shared__ double sh[1024];
     for (int j = 0; j < m; ++j) {
         double v = 0.0;
@@ -408,12 +424,15 @@ __global__ __launch_bounds__(1024) void k_reduce_strided(const double *__restric
         if (threadIdx.x == 0) *(j == 0 ? out0 : out1) = sh[0];
         __syncthreads();
     }
+    if (conv && threadIdx.x == 0 && *out1 <= tol2 * *bb) *state = it;
 }
 
 // x += (rz_old / pq) p;  p = z + (rz_new / rz_old) p
 __global__ __launch_bounds__(256) void k_cg_direction(double *__restrict__ x, double *__restrict__ p,
                                                       const double *__restrict__ z, const double *__restrict__ scal,
-                                                      int i_new, int i_old, int i_pq, int n) {
+                                                      int i_new, int i_old, int i_pq, int n,
+                                                      const int *state = nullptr, int it = 0) {
+    if (cg_skip(state, it)) return;
     const double alpha = scal[i_old] / scal[i_pq];
     const double beta = scal[i_new] / scal[i_old];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -480,6 +499,22 @@ __global__ void k_correct(double *__restrict__ u, const double *__restrict__ ust
     }
 }
 
+// Start of a captured CG: no iteration yet met the tolerance; with a zero
+// right-hand side every iteration is skipped.
+__global__ void k_cg_begin(int *state, const double *bb) {
+    if (threadIdx.x == 0) state[0] = *bb > 0.0 ? INT32_MAX : 0;
+}
+
+// End of a captured CG: rec = {iterations run, relative residual, converged}.
+__global__ void k_cg_end(const int *state, const double *scal, int i_rr, int i_bb, int maxit, double *rec) {
+    if (threadIdx.x != 0) return;
+    const int conv = state[0];
+    const double bb = scal[i_bb];
+    rec[0] = (double)(conv < maxit ? conv : maxit);
+    rec[1] = bb > 0.0 ? sqrt(scal[i_rr] / bb) : 0.0;
+    rec[2] = conv <= maxit ? 1.0 : 0.0;
+}
+
 __global__ void k_zero(double *__restrict__ a, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         a[i] = 0.0;
@@ -523,6 +558,19 @@ struct lesasm_stepper {
     double *sval = nullptr;
     int nslices = 0;
     int64_t sell_entries = 0;
+    int *d_cgstate = nullptr;   // captured CG: iteration that met the tolerance
+};
+
+// A whole time step captured in a HIP graph, bound to one (u, p) pair.
+struct lesasm_step_graph {
+    lesasm_stepper *st = nullptr;
+    double *u = nullptr, *p = nullptr;
+    int cg_iters = 0;
+    double *d_rec = nullptr;        // {iterations, relative residual, converged} of the last replay
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_last = nullptr;   // recorded after every replay
+    bool launched = false;
 };
 
 namespace {
@@ -531,11 +579,8 @@ template <class T> int salloc(lesasm_stepper *st, T **p, size_t n) {
     *p = nullptr;
     if (!n) return LESASM_OK;
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, n * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(LESASM_E_OOM, "stepper: hipMalloc failed");
-    }
+    int rc = device_alloc(&q, n * sizeof(T), "stepper");
+    if (rc) return rc;
     st->allocs.push_back(q);
     *p = (T *)q;
     return LESASM_OK;
@@ -544,7 +589,7 @@ template <class T> int salloc(lesasm_stepper *st, T **p, size_t n) {
 void stepper_free(lesasm_stepper *st) {
     if (!st) return;
     (void)hipDeviceSynchronize();
-    for (void *p : st->allocs) (void)hipFree(p);
+    for (void *p : st->allocs) device_free(p);
     delete st;
 }
 
@@ -605,6 +650,54 @@ int pressure_solve(lesasm_stepper *st, const double *b_in, double *x, hipStream_
     }
     st->last_iters = std::min(it, st->maxit);
     st->last_res = bnorm > 0.0 ? res / bnorm : 0.0;
+    dot(st, x, nullptr, S_SUM, s);
+    hipLaunchKernelGGL(k_sub_mean, dim3(g), dim3(256), 0, s, x, st->scal + S_SUM, n);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+// The same solve for graph capture: no host reads and no copies through the
+// copy engine.  Exactly cg_iters iterations are captured; once the residual
+// meets the tolerance (tested after every iteration, on the device) the
+// remaining iterations return at once.  rec receives the iteration count,
+// relative residual and convergence flag.
+int pressure_solve_captured(lesasm_stepper *st, const double *b_in, double *x, hipStream_t s, int cg_iters,
+                            double *rec) {
+    const int n = st->n;
+    const int g = grid_for(n, 256);
+    hipLaunchKernelGGL(k_lincomb, dim3(g), dim3(256), 0, s, st->b, 1.0, b_in, 0.0, nullptr, 0.0, nullptr, (size_t)n);
+    dot(st, st->b, nullptr, S_SUM, s);
+    hipLaunchKernelGGL(k_sub_mean, dim3(g), dim3(256), 0, s, st->b, st->scal + S_SUM, n);
+    dot(st, st->b, st->b, S_BB, s);
+    hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, s, x, (size_t)n);
+    hipLaunchKernelGGL(k_lincomb, dim3(g), dim3(256), 0, s, st->r, 1.0, st->b, 0.0, nullptr, 0.0, nullptr, (size_t)n);
+    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(256), 0, s, st->z, st->r, st->diag, n);
+    hipLaunchKernelGGL(k_lincomb, dim3(g), dim3(256), 0, s, st->pv, 1.0, st->z, 0.0, nullptr, 0.0, nullptr, (size_t)n);
+    dot(st, st->r, st->z, S_RZ, s);
+    hipLaunchKernelGGL(k_cg_begin, dim3(1), dim3(64), 0, s, st->d_cgstate, st->scal + S_BB);
+    const double tol2 = st->rtol * st->rtol;
+    int i_rz = S_RZ, i_rzn = S_RZN;
+    int *state = st->d_cgstate;
+    for (int it = 1; it <= cg_iters; ++it) {
+        if (st->sval)
+            hipLaunchKernelGGL(k_spmv_sell_dot, dim3(kCgBlocks), dim3(256), 0, s, st->soff, st->scol, st->sval, st->pv,
+                               st->q, n, st->nslices, st->partial, (const int *)state, it);
+        else
+            hipLaunchKernelGGL(k_spmv_dot, dim3(kCgBlocks), dim3(256), 0, s, st->rowptr, st->col, st->val, st->pv,
+                               st->q, n, st->partial, (const int *)state, it);
+        hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 1, 1,
+                           st->scal + S_PQ, st->scal + S_PQ, state, it, false, (const double *)nullptr, 0.0);
+        hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(256), 0, s, st->r, st->z, st->q, st->diag, st->scal,
+                           i_rz, S_PQ, n, st->partial, (const int *)state, it);
+        hipLaunchKernelGGL(k_reduce_strided, dim3(1), dim3(1024), 0, s, st->partial, kCgBlocks, 2, 2,
+                           st->scal + i_rzn, st->scal + S_RR, state, it, true, (const double *)(st->scal + S_BB),
+                           tol2);
+        hipLaunchKernelGGL(k_cg_direction, dim3(kCgBlocks), dim3(256), 0, s, x, st->pv, st->z, st->scal, i_rzn, i_rz,
+                           S_PQ, n, (const int *)state, it);
+        std::swap(i_rz, i_rzn);
+    }
+    hipLaunchKernelGGL(k_cg_end, dim3(1), dim3(64), 0, s, (const int *)state, (const double *)st->scal, (int)S_RR,
+                       (int)S_BB, cg_iters, rec);
     dot(st, x, nullptr, S_SUM, s);
     hipLaunchKernelGGL(k_sub_mean, dim3(g), dim3(256), 0, s, x, st->scal + S_SUM, n);
     LESASM_HIP_TRY(hipGetLastError());
@@ -703,7 +796,7 @@ extern "C" int lesasm_stepper_create(lesasm_mesh *m, double nu, double dt, doubl
         (rc = salloc(st, &st->x, (size_t)n)) || (rc = salloc(st, &st->r, (size_t)n)) ||
         (rc = salloc(st, &st->z, (size_t)n)) || (rc = salloc(st, &st->pv, (size_t)n)) ||
         (rc = salloc(st, &st->q, (size_t)n)) || (rc = salloc(st, &st->partial, 2 * kCgBlocks)) ||
-        (rc = salloc(st, &st->scal, S_NUM)))
+        (rc = salloc(st, &st->scal, S_NUM)) || (rc = salloc(st, &st->d_cgstate, 4)))
         return rc;
     if (n) {
         LESASM_HIP_TRY(hipMemcpy(st->rowptr, rowptr.data(), sizeof(int32_t) * rowptr.size(), hipMemcpyHostToDevice));
@@ -756,7 +849,7 @@ extern "C" int lesasm_stepper_create(lesasm_mesh *m, double nu, double dt, doubl
                 LESASM_HIP_TRY(hipGetLastError());
                 LESASM_HIP_TRY(hipDeviceSynchronize());
                 st->allocs.erase(std::find(st->allocs.begin(), st->allocs.end(), (void *)d_src));
-                (void)hipFree(d_src);
+                device_free(d_src);
                 st->nslices = ns;
                 st->sell_entries = total;
             }
@@ -835,13 +928,10 @@ extern "C" int lesasm_stepper_rk3_stages(lesasm_stepper *st, const double *d_u, 
     return rk3_stages(st, d_u, d_p, d_ustar, (hipStream_t)stream);
 }
 
-extern "C" int lesasm_stepper_step(lesasm_stepper *st, double *d_u, double *d_p, void *stream) {
-    if (!st || (st->n && (!d_u || !d_p))) return fail(LESASM_E_INVALID_ARG, "stepper_step: NULL argument");
-    int dev = -1;
-    LESASM_HIP_TRY(hipGetDevice(&dev));
-    if (dev != st->mesh->device) return fail(LESASM_E_STATE, "stepper_step: wrong current device");
-    if (!st->n) return LESASM_OK;
-    hipStream_t s = (hipStream_t)stream;
+// One time step on s: the stages, b = -(1/dt) D u*, the pressure solve (eager
+// with host convergence checks, or captured with cg_iters device-terminated
+// iterations when rec is given), the correction and the pressure update.
+static int step_body(lesasm_stepper *st, double *d_u, double *d_p, hipStream_t s, int cg_iters, double *rec) {
     lesasm_mesh *m = st->mesh;
     const int n = st->n;
     int rc;
@@ -850,13 +940,120 @@ extern "C" int lesasm_stepper_step(lesasm_stepper *st, double *d_u, double *d_p,
     if ((rc = lesasm_divergence(m, st->ustar, st->q, s))) return rc;
     hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, 256)), dim3(256), 0, s, st->q, -1.0 / st->dt, st->q, 0.0, nullptr,
                        0.0, nullptr, (size_t)n);
-    if ((rc = pressure_solve(st, st->q, st->x, s))) return rc;
+    if (rec) rc = pressure_solve_captured(st, st->q, st->x, s, cg_iters, rec);
+    else rc = pressure_solve(st, st->q, st->x, s);
+    if (rc) return rc;
     if ((rc = lesasm_gradient(m, st->x, st->gdp, s))) return rc;
     hipLaunchKernelGGL(k_correct, dim3(grid_for(n, 256)), dim3(256), 0, s, d_u, st->ustar, st->gdp, m->d_mass,
                        st->dt, n);
     hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, 256)), dim3(256), 0, s, d_p, 1.0, d_p, 1.0, st->x, 0.0, nullptr,
                        (size_t)n);
     LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_stepper_step(lesasm_stepper *st, double *d_u, double *d_p, void *stream) {
+    if (!st || (st->n && (!d_u || !d_p))) return fail(LESASM_E_INVALID_ARG, "stepper_step: NULL argument");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != st->mesh->device) return fail(LESASM_E_STATE, "stepper_step: wrong current device");
+    if (!st->n) return LESASM_OK;
+    return step_body(st, d_u, d_p, (hipStream_t)stream, 0, nullptr);
+}
+
+// ---- step graph ----------------------------------------------------------------
+
+static void step_graph_free(lesasm_step_graph *g) {
+    if (!g) return;
+    // a replay may still be queued: wait for the last one before the
+    // executable graph goes away
+    if (g->launched && g->ev_last) (void)hipEventSynchronize(g->ev_last);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ev_last) (void)hipEventDestroy(g->ev_last);
+    device_free(g->d_rec);
+    delete g;
+}
+
+extern "C" int lesasm_step_graph_create(lesasm_stepper *st, double *d_u, double *d_p, int cg_iters,
+                                        lesasm_step_graph **out, void *stream) {
+    if (!out) return fail(LESASM_E_INVALID_ARG, "step_graph_create: out is NULL");
+    *out = nullptr;
+    if (!st || !d_u || !d_p) return fail(LESASM_E_INVALID_ARG, "step_graph_create: NULL argument");
+    if (cg_iters < 1 || cg_iters > kMaxCapturedCg)
+        return fail(LESASM_E_INVALID_ARG, "step_graph_create: cg_iters must be in 1.." + std::to_string(kMaxCapturedCg));
+    if (!st->n) return fail(LESASM_E_INVALID_ARG, "step_graph_create: the mesh has no field nodes");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(LESASM_E_INVALID_ARG, "step_graph_create: capture needs a non-default stream");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != st->mesh->device) return fail(LESASM_E_STATE, "step_graph_create: wrong current device");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    LESASM_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(LESASM_E_STATE, "step_graph_create: stream is already capturing");
+    auto *g = new lesasm_step_graph();
+    struct Guard {
+        lesasm_step_graph *p;
+        ~Guard() { step_graph_free(p); }
+    } guard{g};
+    g->st = st;
+    g->u = d_u;
+    g->p = d_p;
+    g->cg_iters = cg_iters;
+    {
+        void *q = nullptr;
+        const int rc = device_alloc(&q, 4 * sizeof(double), "step graph");
+        if (rc) return rc;
+        g->d_rec = (double *)q;
+    }
+    LESASM_HIP_TRY(hipEventCreateWithFlags(&g->ev_last, hipEventDisableTiming));
+    // the mesh's previous work must not overlap the capture's first launches
+    LESASM_HIP_TRY(hipStreamSynchronize(s));
+    LESASM_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = step_body(st, d_u, d_p, s, cg_iters, g->d_rec);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LESASM_E_HIP, std::string("step_graph_create: capture failed: ") + hipGetErrorString(e));
+    g->graph = graph;
+    LESASM_HIP_TRY(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+    guard.p = nullptr;
+    *out = g;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_step_graph_launch(lesasm_step_graph *g, double *d_u, double *d_p, void *stream) {
+    if (!g) return fail(LESASM_E_INVALID_ARG, "step_graph_launch: graph is NULL");
+    if (d_u != g->u || d_p != g->p)
+        return fail(LESASM_E_STATE, "step_graph_launch: u and p must be the buffers the graph was captured with");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != g->st->mesh->device) return fail(LESASM_E_STATE, "step_graph_launch: wrong current device");
+    hipStream_t s = (hipStream_t)stream;
+    LESASM_HIP_TRY(hipGraphLaunch(g->exec, s));
+    LESASM_HIP_TRY(hipEventRecord(g->ev_last, s));
+    g->launched = true;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_step_graph_stats(lesasm_step_graph *g, int *cg_iters, double *cg_rel_residual, int *converged) {
+    if (!g || !cg_iters || !cg_rel_residual || !converged)
+        return fail(LESASM_E_INVALID_ARG, "step_graph_stats: NULL argument");
+    if (!g->launched) return fail(LESASM_E_STATE, "step_graph_stats: the graph has not been launched");
+    LESASM_HIP_TRY(hipEventSynchronize(g->ev_last));
+    double rec[3] = {0.0, 0.0, 0.0};
+    LESASM_HIP_TRY(hipMemcpy(rec, g->d_rec, sizeof(rec), hipMemcpyDeviceToHost));
+    *cg_iters = (int)rec[0];
+    *cg_rel_residual = rec[1];
+    *converged = rec[2] != 0.0;
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_step_graph_destroy(lesasm_step_graph *g) {
+    step_graph_free(g);
     return LESASM_OK;
 }
 

@@ -39,8 +39,11 @@ EXPORTS = [
     "lesasm_batch_rk3_eager", "lesasm_mlp_create", "lesasm_mlp_destroy", "lesasm_mlp_get_params",
     "lesasm_mlp_set_params", "lesasm_mlp_loss_grad", "lesasm_mlp_adam", "lesasm_mlp_train_step", "lesasm_mlp_commit",
     "lesasm_mlp_forward_f32", "lesasm_mlp_infer_bf16", "lesasm_mesh_set_closure", "lesasm_mesh_closure_fallbacks",
+    "lesasm_mesh_closure_fallbacks_by_type",
     "lesasm_element_centroids", "lesasm_sfc_workspace_bytes", "lesasm_sfc_partition", "lesasm_balance_update",
     "lesasm_batch_set_per_type", "lesasm_batch_get_per_type",
+    "lesasm_step_graph_create", "lesasm_step_graph_launch", "lesasm_step_graph_stats", "lesasm_step_graph_destroy",
+    "lesasm_set_memory_cap", "lesasm_memory_in_use",
 ]
 MLP_PARAMS = 5254
 ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
@@ -108,10 +111,14 @@ def load(path: str = LIB_PATH):
         "lesasm_mlp_adam": [P, P, ctypes.c_float, P], "lesasm_mlp_train_step": [P, P, P, I, ctypes.c_float, P, P],
         "lesasm_mlp_commit": [P], "lesasm_mlp_forward_f32": [P, P, I, P, P], "lesasm_mlp_infer_bf16": [P, P, I, P, P],
         "lesasm_mesh_set_closure": [P, P, D, D], "lesasm_mesh_closure_fallbacks": [P, P],
+        "lesasm_mesh_closure_fallbacks_by_type": [P, P],
         "lesasm_element_centroids": [I64, P, P, I64, I64, P, P, P, P, P],
         "lesasm_sfc_workspace_bytes": [I64, I, I, P], "lesasm_sfc_partition": [I64, P, P, I, P, I, P, ctypes.c_size_t, P, P],
         "lesasm_balance_update": [I, I, P, P, D, P],
         "lesasm_batch_set_per_type": [P, I], "lesasm_batch_get_per_type": [P, P],
+        "lesasm_step_graph_create": [P, P, P, I, P, P], "lesasm_step_graph_launch": [P, P, P, P],
+        "lesasm_step_graph_stats": [P, P, P, P], "lesasm_step_graph_destroy": [P],
+        "lesasm_set_memory_cap": [ctypes.c_uint64], "lesasm_memory_in_use": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -348,6 +355,52 @@ class Stepper:
         check(load().lesasm_stepper_laplacian(self._h, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data,
                                               ctypes.byref(nnz)))
         return rowptr, col, val
+
+
+def set_memory_cap(nbytes: int):
+    """Cap on the device memory the library allocates (0: none)."""
+    check(load().lesasm_set_memory_cap(int(nbytes)))
+
+
+def memory_in_use() -> int:
+    """Device bytes the library holds now."""
+    v = ctypes.c_uint64()
+    check(load().lesasm_memory_in_use(ctypes.byref(v)))
+    return v.value
+
+
+class StepGraph:
+    """One whole time step of a Stepper captured in a HIP graph
+    (lesasm_step_graph_*), bound to the tensors u [n,3] and p [n] (internal
+    order), which every replay updates in place."""
+
+    def __init__(self, stepper: "Stepper", u, p, cg_iters: int, stream):
+        stepper.mesh._field(u)
+        stepper.mesh._field(p)
+        self.stepper, self.u, self.p = stepper, u, p
+        h = ctypes.c_void_p()
+        check(load().lesasm_step_graph_create(stepper._h, _ptr(u), _ptr(p), int(cg_iters), ctypes.byref(h),
+                                              stream.cuda_stream))
+        self._h = h
+
+    def launch(self, stream=None, u=None, p=None):
+        """Replay on `stream` (default: torch's current stream).  Passing other
+        tensors than the bound ones is rejected by the library."""
+        u = self.u if u is None else u
+        p = self.p if p is None else p
+        s = _stream() if stream is None else stream.cuda_stream
+        check(load().lesasm_step_graph_launch(self._h, _ptr(u), _ptr(p), s))
+
+    def stats(self):
+        """(CG iterations, relative residual, converged) of the last replay."""
+        it, res, ok = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+        check(load().lesasm_step_graph_stats(self._h, ctypes.byref(it), ctypes.byref(res), ctypes.byref(ok)))
+        return it.value, res.value, bool(ok.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(load().lesasm_step_graph_destroy(self._h))
+            self._h = None
 
 
 def check_stream(stream=None):
@@ -590,3 +643,11 @@ def closure_fallbacks(mesh: Mesh) -> int:
     v = ctypes.c_uint64()
     check(load().lesasm_mesh_closure_fallbacks(mesh._h, ctypes.byref(v)))
     return v.value
+
+
+def closure_fallbacks_by_type(mesh: Mesh) -> dict:
+    """Elements per type (4, 5, 6, 8) that kept Vreman's stress since the last
+    call (resets the counts)."""
+    v = (ctypes.c_uint64 * 4)()
+    check(load().lesasm_mesh_closure_fallbacks_by_type(mesh._h, v))
+    return {4: int(v[0]), 5: int(v[1]), 6: int(v[2]), 8: int(v[3])}

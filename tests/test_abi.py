@@ -89,3 +89,14 @@ def test_invalid_descriptions_are_rejected_before_any_gpu_call(lib):
     assert lib.lesasm_mesh_create(None, ctypes.byref(h)) == lesasm.E_INVALID_ARG
     assert lib.lesasm_assemble_momentum_rhs(None, None, None, 0.0, 0.0, None, None) == lesasm.E_INVALID_ARG
     assert lib.lesasm_mesh_destroy(None) == lesasm.OK
+
+
+def test_memory_cap_and_count_without_gpu(lib):
+    # host-side bookkeeping: nothing allocated yet in this process, the cap is
+    # set and cleared without a GPU
+    import ctypes as C
+    v = C.c_uint64(123)
+    assert lib.lesasm_memory_in_use(C.byref(v)) == 0 and v.value == 0
+    assert lib.lesasm_set_memory_cap(1 << 20) == 0
+    assert lib.lesasm_set_memory_cap(0) == 0
+    assert lib.lesasm_memory_in_use(None) == -1

@@ -65,3 +65,17 @@ def test_partition_byte_counts():
     assert nb["centroids"] == 8 * 3 + 4 * 16 + 24 * 12 + 28 * 2
     assert nb["split"] == 64 * 2 + 8 * 8 * 6
     assert np.isfinite(list(nb.values())).all()
+
+
+def test_cpu_baseline_uses_the_threads_it_reports(monkeypatch):
+    # the all-core leg runs the oracle's threaded assembly on OMP_NUM_THREADS
+    # threads (the CPU share of the process) and says so, with the host model
+    c = mg.small_hybrid_case(nx=4, ny=3, seed=5)
+    monkeypatch.setenv("OMP_NUM_THREADS", "3")
+    assert bench.baseline_threads() == 3
+    cb = bench.cpu_baseline(c, single_thread_s=0.5, min_cpu_seconds=0.0, max_reps=2)
+    assert cb["cores"] == 3 and cb["kind"] == "oracle" and cb["value"] > 0
+    assert "3 threads" in cb["sample"] and cb["host"]["logical_cpus"] >= 1
+    assert abs(cb["single_thread"]["value"] - c.mesh.n_elems / 0.5) < 1e-9
+    monkeypatch.delenv("OMP_NUM_THREADS")
+    assert bench.baseline_threads() == len(os.sched_getaffinity(0))

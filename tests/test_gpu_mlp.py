@@ -122,11 +122,16 @@ def test_fused_closure_matches_oracle(torch_cuda, net, precision):
     u = mesh.to_internal(torch.from_numpy(c.u).cuda())
     pp = mesh.to_internal(torch.from_numpy(c.p).cuda())
     got = mesh.to_user(mesh.assemble_momentum_rhs(u, pp, c.nu)).cpu().numpy()
-    nfb = lesasm.closure_fallbacks(mesh)
+    by_type = lesasm.closure_fallbacks_by_type(mesh)
+    nfb = sum(by_type.values())
     ref, use, eps = closure.assemble(c.mesh, c.u, c.p, c.nu, c.vreman_c, p, delta_ref, tol)
-    near = int(((eps > tol * 0.99) & (eps < tol * 1.01)).sum())
+    near_el = (eps > tol * 0.99) & (eps < tol * 1.01)
+    near = int(near_el.sum())
     print(f"  {precision}: fallbacks gpu {nfb}, oracle {int((~use).sum())} of {len(use)}, near threshold {near}")
     assert abs(nfb - int((~use).sum())) <= near
+    for t in (mg.TET04, mg.PYR05, mg.PEN06, mg.HEX08):  # the same per element type
+        of_t = c.mesh.types == t
+        assert abs(by_type[t] - int((~use & of_t).sum())) <= int((near_el & of_t).sum()), t
     for i in range(3):
         d = np.linalg.norm(got[:, i] - ref[:, i]) / np.linalg.norm(ref[:, i])
         assert d <= 1e-3, (i, d)
