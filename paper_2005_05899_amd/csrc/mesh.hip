@@ -436,7 +436,6 @@ static int build_scatter(lesasm_mesh *m) {
         if ((st = device_side_streams(m->device, m->side))) return st;
         for (int i = 0; i < 3; ++i) LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming));
         LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
-        LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming));
     }
     return LESASM_OK;
 }
@@ -643,6 +642,8 @@ extern "C" int lesasm_mesh_create(const lesasm_mesh_desc *d, lesasm_mesh **out) 
         const std::vector<int32_t> &cf = c.h_cf.empty() ? c.h_cg : c.h_cf;
         for (int32_t f : cf) m->h_finc[f]++;
     }
+    // every scatter mode orders its calls through this event
+    LESASM_HIP_TRY(hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming));
     if (is_chunked(m) && (st = build_scatter(m))) return st;
 
     // geometry: det J check, Delta_e, lumped mass
