@@ -17,8 +17,14 @@ from . import mlp as _mlp
 from . import oracle as _o
 
 
-def assemble(mesh, u, p, nu, c, params: dict, delta_ref: float, tol: float = 0.05, bf16: bool = True):
-    """Returns (rhs [n_field, 3], use_mlp [n_elems] bool, eps [n_elems])."""
+def assemble(mesh, u, p, nu, c, params: dict, delta_ref: float, tol: float = 0.05, bf16: bool = True,
+             parts: bool = False):
+    """Returns (rhs [n_field, 3], use_mlp [n_elems] bool, eps [n_elems]).
+
+    parts=True appends a dict of diagnostics (the residual is unchanged):
+    "share" [n_field, 3], the network's own stress term int dN_a/dx_j tau_m
+    assembled over the kept elements, and "D", the list of per-element
+    stress-difference vectors [n_a, 3] (element order)."""
     coords, types, offs, conn, fn, nf = _o._mesh_args(mesh)
     ne = len(types)
     recs, RV, deltas = [], [], np.zeros(ne)
@@ -43,14 +49,22 @@ def assemble(mesh, u, p, nu, c, params: dict, delta_ref: float, tol: float = 0.0
     rhs = np.zeros((nf, 3))
     use = np.zeros(ne, bool)
     eps = np.zeros(ne)
+    share = np.zeros((nf, 3)) if parts else None
+    d_list = []
     o = 0
     for e in range(ne):
         nodes = conn[offs[e]:offs[e + 1]]
         f = nodes if fn is None else fn[nodes]
         D = _o.element_stress_residual(int(types[e]), coords[nodes], dtau[o:o + ng[e]])
-        o += ng[e]
         nr = np.linalg.norm(RV[e])
         eps[e] = np.linalg.norm(D) / nr if nr > 0 else np.inf
         use[e] = np.linalg.norm(D) ** 2 <= tol * tol * nr * nr
         np.add.at(rhs, f, RV[e] + D if use[e] else RV[e])
+        if parts:
+            d_list.append(D)
+            if use[e]:
+                np.add.at(share, f, _o.element_stress_residual(int(types[e]), coords[nodes], tau_m[o:o + ng[e]]))
+        o += ng[e]
+    if parts:
+        return rhs, use, eps, {"share": share, "D": d_list}
     return rhs, use, eps

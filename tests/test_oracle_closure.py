@@ -124,6 +124,39 @@ def test_vreman_network_on_a_trace_free_linear_field_keeps_every_element(orc, ca
     assert np.abs(rhs - want).max() <= 1e-12 * np.abs(want).max()
 
 
+def test_parts_hold_the_network_stress_term_and_the_differences(orc, case, monkeypatch):
+    # diagnostics of the closure oracle (the tolerance of the GPU closure tests
+    # is built from them): with the Vreman stand-in on a trace-free linear
+    # field every element is kept and the network's stress term is Vreman's,
+    # i.e. the subgrid term of the plain assembly; the per-element differences
+    # assemble to the closure residual minus the plain one
+    m = case.mesh
+    rng = np.random.default_rng(33)
+    A = rng.standard_normal((3, 3))
+    A -= np.trace(A) / 3.0 * np.eye(3)
+    u = m.field_coords() @ A.T + rng.standard_normal(3)
+    c = 0.13
+    monkeypatch.setattr(CL._mlp, "forward_bf16", _vreman_network(c))
+    rhs, use, eps, parts = CL.assemble(m, u, case.p, case.nu, c, _params(9), _width_ref(m), tol=math.inf,
+                                       parts=True)
+    assert use.all()
+    sgs = orc.assemble(m, u, case.p, case.nu, c, terms=orc.TERM_SGS)
+    assert np.abs(sgs).max() > 0
+    assert np.abs(parts["share"] - sgs).max() <= 1e-12 * np.abs(sgs).max()
+    monkeypatch.undo()
+    rhs, use, eps, parts = CL.assemble(m, case.u, case.p, case.nu, case.vreman_c, _params(5, 0.05), _width_ref(m),
+                                       tol=math.inf, parts=True)
+    assert use.all() and len(parts["D"]) == m.n_elems
+    dsum = np.zeros_like(rhs)
+    fn = m.field_node
+    for e in range(m.n_elems):
+        nodes = m.conn[m.conn_offsets[e]:m.conn_offsets[e + 1]]
+        np.add.at(dsum, nodes if fn is None else fn[nodes], parts["D"][e])
+    plain = orc.assemble(m, case.u, case.p, case.nu, case.vreman_c)
+    assert np.abs(dsum).max() > 1e-6 * np.abs(plain).max()
+    assert np.abs(plain + dsum - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
 def test_vreman_network_leaves_the_trace_term(orc, case, monkeypatch):
     # tau_m - tau_v = dev(tau_v) - tau_v = -(tr tau_v / 3) I = (2/3) nu_t div(u) I
     m = case.mesh
