@@ -290,6 +290,9 @@ def kernel_table(mesh, m, kt, peak) -> dict:
     return table
 
 
+WARM_SECONDS = 0.3
+
+
 def profile_kernels(torch, mesh, u, p, nu, steps, concurrent):
     """Per-kernel HIP-event durations of `steps` assemblies, recorded by the
     library on the stream each kernel is launched on.  concurrent=False runs
@@ -297,9 +300,15 @@ def profile_kernels(torch, mesh, u, p, nu, steps, concurrent):
     from paper_2005_05899_amd import lesasm
     rhs = torch.empty_like(u)
     mesh.set_option(lesasm.OPT_CONCURRENT, 1 if concurrent else 0)
-    for _ in range(2):
-        mesh.assemble_momentum_rhs(u, p, nu, out=rhs)
-    torch.cuda.synchronize()
+    # uninstrumented assemblies for at least WARM_SECONDS first, so that the
+    # clocks have settled before the first recorded launch
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(4):
+            mesh.assemble_momentum_rhs(u, p, nu, out=rhs)
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= WARM_SECONDS:
+            break
     mesh.set_option(lesasm.OPT_PROFILE, 1)
     mesh.kernel_times(reset=True)
     for _ in range(steps):
