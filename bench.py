@@ -320,7 +320,50 @@ def profile_kernels(torch, mesh, u, p, nu, steps, concurrent):
     return kt
 
 
-def measure_workload(torch, args, workload, case, variants: bool, oracle_errors: bool):
+def closure_delta_ref(mesh, meta: dict) -> float:
+    """Width reference handed to the learned closure: the mesh's geometric
+    mean Delta_e when the network was trained with that rule (recorded in its
+    metadata), else the fixed reference the metadata holds."""
+    from paper_2005_05899_amd import training
+    if meta.get("delta_ref_rule"):
+        return training.mesh_delta_ref(mesh)
+    return meta.get("delta_ref", 0.1)
+
+
+def closure_variants(torch, args, mesh, m, case, u, p, elapsed, ref, precisions=("fp32", "fp64")) -> dict:
+    """The fused learned closure (committed network, 5 % fallback rule) in the
+    given contraction precisions: rate, speed against plain FP64 Vreman,
+    network rate on the matrix cores, fallback fraction per type, difference
+    from the FP64 Vreman oracle."""
+    from paper_2005_05899_amd import lesasm
+    vr = {}
+    if not os.path.exists(WEIGHTS):
+        return vr
+    E = m.n_elems
+    params = np.load(WEIGHTS)
+    meta = json.load(open(WEIGHTS_META)) if os.path.exists(WEIGHTS_META) else {}
+    net = lesasm.MLP(params)
+    dref = closure_delta_ref(mesh, meta)
+    for prec in precisions:
+        mesh.precision = prec
+        lesasm.set_closure(mesh, net, dref, 0.05)
+        el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
+        npts = sum(int((m.types == t).sum()) * GAUSS[t] for t in GAUSS)
+        mfma_tf = npts * MLP_FLOPS_PER_POINT * args.steps / el / 1e12
+        vr[f"learned_closure_{prec}"] = {
+            "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+            "speedup_vs_fp64_vreman": elapsed / el, "delta_ref": dref,
+            "network_bf16_tflops": mfma_tf, "network_frac_of_bf16_peak": mfma_tf / BF16_MATRIX_PEAK_TFLOPS,
+            "fallback_fraction": fallback_fraction(mesh, u, p, case.nu),
+            "difference_vs_fp64_vreman_oracle": None if ref is None else
+            field_errors(mesh.to_user(rl).cpu().numpy(), ref)}
+        lesasm.set_closure(mesh, None)
+    net.close()
+    mesh.precision = args.precision
+    return vr
+
+
+def measure_workload(torch, args, workload, case, variants: bool, oracle_errors: bool, closure: bool = False):
     """One workload: per-kernel isolated durations, graph replay, then the
     timed region (W warm-up assemblies, K timed ones between two
     synchronisations, no instrumentation), then the concurrent per-kernel
@@ -396,27 +439,13 @@ def measure_workload(torch, args, workload, case, variants: bool, oracle_errors:
         vr["fp32_contractions"] = {"value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
                                    "speedup_vs_fp64": elapsed / el,
                                    "error_vs_fp64_oracle": field_errors(mesh.to_user(r32).cpu().numpy(), ref)}
-        if os.path.exists(WEIGHTS):
-            params = np.load(WEIGHTS)
-            meta = json.load(open(WEIGHTS_META)) if os.path.exists(WEIGHTS_META) else {}
-            net = lesasm.MLP(params)
-            for prec in ("fp32", "fp64"):
-                mesh.precision = prec
-                lesasm.set_closure(mesh, net, meta.get("delta_ref", 0.1), 0.05)
-                el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
-                npts = sum(int((m.types == t).sum()) * GAUSS[t] for t in GAUSS)
-                mfma_tf = npts * MLP_FLOPS_PER_POINT * args.steps / el / 1e12
-                vr[f"learned_closure_{prec}"] = {
-                    "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-                    "speedup_vs_fp64_vreman": elapsed / el,
-                    "network_bf16_tflops": mfma_tf, "network_frac_of_bf16_peak": mfma_tf / BF16_MATRIX_PEAK_TFLOPS,
-                    "fallback_fraction": fallback_fraction(mesh, u, p, case.nu),
-                    "difference_vs_fp64_vreman_oracle": field_errors(mesh.to_user(rl).cpu().numpy(), ref)}
-                lesasm.set_closure(mesh, None)
-            net.close()
+        vr.update(closure_variants(torch, args, mesh, m, case, u, p, elapsed, ref))
         mesh.precision = args.precision
         rec["variants"] = vr
         rec["wall_model"] = time_wall(torch, mesh, m, case, u, args.steps)
+    elif closure:
+        rec["variants"] = closure_variants(torch, args, mesh, m, case, u, p, elapsed, ref if oracle_errors else None,
+                                           precisions=("fp32",))
     mesh.close()
     return rec, t_oracle
 
@@ -451,7 +480,7 @@ def run_main(args):
         # the 2.0 M-element mesh of the same generator as a sub-record (FP64, same protocol)
         t1 = time.time()
         small = make_case("hybrid2m")
-        sub, _ = measure_workload(torch, args, "hybrid2m", small, False, True)
+        sub, _ = measure_workload(torch, args, "hybrid2m", small, False, True, closure=True)
         sub.pop("kernels_concurrent")
         out["hybrid2m"] = sub
         print(f"  hybrid2m sub-record ({time.time() - t1:.0f} s)", file=sys.stderr, flush=True)
@@ -620,9 +649,10 @@ def run_precision(args):
         params = np.load(WEIGHTS)
         meta = json.load(open(WEIGHTS_META)) if os.path.exists(WEIGHTS_META) else {}
         net = lesasm.MLP(params)
+        dref = closure_delta_ref(mesh, meta)
         for prec in ("fp32", "fp64"):
             mesh.precision = prec
-            lesasm.set_closure(mesh, net, meta.get("delta_ref", 0.1), 0.05)
+            lesasm.set_closure(mesh, net, dref, 0.05)
             el, _, rl = time_assembly(torch, mesh, u, p, case.nu, args.steps, args.warmup)
             variants[f"learned_closure_{prec}"] = {
                 "value": E * args.steps / el, "ms_per_step": 1e3 * el / args.steps,

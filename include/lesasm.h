@@ -333,9 +333,11 @@ int lesasm_batch_get_config(const lesasm_batch *batch, int *chunk, int *order, i
  * whole queue, switching on the element type of each item; 1 the queue is
  * ordered type by type (the chosen order kept inside each type) and four
  * persistent kernels, one per element type (each compiled, and resident, for
- * its own type), drain their parts concurrently on forked streams.  Rebuilds
+ * its own type), drain their parts concurrently on forked streams; 2 the same
+ * type-ordered queue and four kernels, but one workgroup per item, scheduled
+ * by the hardware (no queue counter; grid_per_cu does not apply).  Rebuilds
  * the queue (synchronises).  Errors: LESASM_E_INVALID_ARG, LESASM_E_UNSUPPORTED
- * (a value other than 0 or 1). */
+ * (a value other than 0, 1 or 2). */
 int lesasm_batch_set_per_type(lesasm_batch *batch, int per_type);
 int lesasm_batch_get_per_type(const lesasm_batch *batch, int *per_type);
 
@@ -352,8 +354,8 @@ int lesasm_batch_assemble(lesasm_batch *batch, const double *const *d_u, const d
 
 /* Autotuner: times the batched assembly for chunk lengths {128, 256, 512,
  * 1024} x the three queue orders x {2, 4} workgroups per compute unit x the
- * two kernel layouts (median of `reps` runs after one warm-up) and keeps the
- * fastest.  With a cache_path, a line "signature chunk order grid per_type
+ * three kernel layouts (the third without a grid size; median of `reps` runs
+ * after one warm-up) and keeps the fastest.  With a cache_path, a line "signature chunk order grid per_type
  * ms" is looked up first
  * (signature = compute units and element counts per mesh and type) and
  * appended after tuning.  *best_ms receives the time.  Synchronises. */

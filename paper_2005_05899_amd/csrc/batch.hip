@@ -90,10 +90,12 @@ __global__ __launch_bounds__(256) void k_batch_assemble(const BatchEntry *__rest
     }
 }
 
-// Per-type persistent kernel: the same queue walk over the items of one
-// element type only, so each type is compiled (and occupies registers) on
-// its own and the four run concurrently.
-template <int T, typename R, bool HAS_P>
+// Per-type kernel: the same walk over the items of one element type only, so
+// each type is compiled (and occupies registers) on its own and the four run
+// concurrently.  PERSISTENT: a grid sized to fill the GPU pulls items from the
+// type's counter; otherwise one workgroup per item (item order remapped so
+// that each XCD takes a contiguous run), scheduled by the hardware.
+template <int T, typename R, bool HAS_P, bool PERSISTENT>
 __global__ __launch_bounds__(256) void k_batch_assemble_type(const BatchEntry *__restrict__ entries,
                                                              const BatchCall *__restrict__ call,
                                                              const int32_t *__restrict__ wentry,
@@ -101,15 +103,21 @@ __global__ __launch_bounds__(256) void k_batch_assemble_type(const BatchEntry *_
     extern __shared__ __align__(16) double lds[];
     __shared__ int item;
     for (;;) {
-        if (threadIdx.x == 0) item = atomicAdd(head, 1);
-        __syncthreads();
-        const int w = item;
-        __syncthreads();
+        int w;
+        if constexpr (PERSISTENT) {
+            if (threadIdx.x == 0) item = atomicAdd(head, 1);
+            __syncthreads();
+            w = item;
+            __syncthreads();
+        } else {
+            w = xcd_block(blockIdx.x, gridDim.x);
+        }
         if (w >= nwork) return;
         const BatchEntry &be = entries[wentry[w]];
         const int mi = be.mesh;
         chunk_body<T, R, HAS_P, false, true>(be.v, wchunk[w], lds, be.xyz, call->u[mi], HAS_P ? call->p[mi] : nullptr,
                                              call->nu[mi], be.cv, call->rhs[mi]);
+        if constexpr (!PERSISTENT) return;
         __syncthreads();
     }
 }
@@ -419,17 +427,33 @@ template <int T>
 void launch_type(lesasm_batch *b, int k, bool has_p, bool fp32, hipStream_t s) {
     const int n = b->type_off[k + 1] - b->type_off[k];
     if (n <= 0) return;
-    const int grid = std::max(1, std::min(n, b->n_cu * b->grid_per_cu));
+    const bool persistent = b->per_type == 1;
+    // persistent: a grid that fills the GPU; else one workgroup per item
+    const int grid = persistent ? std::max(1, std::min(n, b->n_cu * b->grid_per_cu)) : n;
     const size_t shm = sizeof(double) * (size_t)b->type_lds[k];
     const int32_t *we = b->d_wentry + b->type_off[k], *wc = b->d_wchunk + b->type_off[k];
     int *head = b->d_head + 1 + k;
-    if (fp32) {
-        if (has_p) hipLaunchKernelGGL((k_batch_assemble_type<T, float, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
-        else hipLaunchKernelGGL((k_batch_assemble_type<T, float, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
+#define LESASM_BATCH_TYPE_LAUNCH(RR, HP, PS)                                                                          \
+    hipLaunchKernelGGL((k_batch_assemble_type<T, RR, HP, PS>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, \
+                       we, wc, n, head)
+    if (persistent) {
+        if (fp32) {
+            if (has_p) LESASM_BATCH_TYPE_LAUNCH(float, true, true);
+            else LESASM_BATCH_TYPE_LAUNCH(float, false, true);
+        } else {
+            if (has_p) LESASM_BATCH_TYPE_LAUNCH(double, true, true);
+            else LESASM_BATCH_TYPE_LAUNCH(double, false, true);
+        }
     } else {
-        if (has_p) hipLaunchKernelGGL((k_batch_assemble_type<T, double, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
-        else hipLaunchKernelGGL((k_batch_assemble_type<T, double, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, we, wc, n, head);
+        if (fp32) {
+            if (has_p) LESASM_BATCH_TYPE_LAUNCH(float, true, false);
+            else LESASM_BATCH_TYPE_LAUNCH(float, false, false);
+        } else {
+            if (has_p) LESASM_BATCH_TYPE_LAUNCH(double, true, false);
+            else LESASM_BATCH_TYPE_LAUNCH(double, false, false);
+        }
     }
+#undef LESASM_BATCH_TYPE_LAUNCH
 }
 
 int batch_launch(lesasm_batch *b, const BatchCall &call, bool has_p, bool fp32, hipStream_t s) {
@@ -566,7 +590,7 @@ extern "C" int lesasm_batch_get_config(const lesasm_batch *b, int *chunk, int *o
 
 extern "C" int lesasm_batch_set_per_type(lesasm_batch *b, int per_type) {
     if (!b) return fail(LESASM_E_INVALID_ARG, "batch_set_per_type: batch is NULL");
-    if (per_type != 0 && per_type != 1) return fail(LESASM_E_UNSUPPORTED, "batch_set_per_type: 0 or 1");
+    if (per_type < 0 || per_type > 2) return fail(LESASM_E_UNSUPPORTED, "batch_set_per_type: 0, 1 or 2");
     b->per_type = per_type;
     return rebuild(b);
 }
@@ -602,7 +626,7 @@ extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, cons
                                  double *best_ms) {
     if (!b || !d_u || !nu || !d_rhs || reps < 1) return fail(LESASM_E_INVALID_ARG, "batch_tune: bad argument");
     std::ostringstream sig;
-    sig << "v2_cu" << b->n_cu;
+    sig << "v3_cu" << b->n_cu;
     for (lesasm_mesh *m : b->meshes)
         for (int k = 0; k < kNumCat; ++k) sig << "_" << m->cat[k].n;
     const std::string key = sig.str();
@@ -637,7 +661,8 @@ extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, cons
     for (int c : chunks)
         for (int o : orders)
             for (int g : grids)
-                for (int pt = 0; pt < 2; ++pt) {
+                for (int pt = 0; pt < 3; ++pt) {
+                    if (pt == 2 && g != grids[0]) continue;  // one workgroup per item: no grid size to choose
                     b->chunk = c;
                     b->order = o;
                     b->grid_per_cu = g;

@@ -7,6 +7,7 @@ fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -47,6 +48,34 @@ EXPORTS = [
 ]
 MLP_PARAMS = 5254
 ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
+
+
+# Library objects dropped by the garbage collector are not destroyed from the
+# collector: a destroy synchronises the device, which must not happen while the
+# caller is capturing a stream.  __del__ only queues the handle; queued handles
+# are destroyed at the next object creation or explicit close() and at exit,
+# step graphs before steppers before batches before meshes before networks.
+_DESTROY_ORDER = {"lesasm_step_graph_destroy": 0, "lesasm_stepper_destroy": 1, "lesasm_batch_destroy": 2,
+                  "lesasm_mesh_destroy": 3, "lesasm_mlp_destroy": 4}
+_deferred: list = []
+
+
+def _defer(fn: str, h) -> None:
+    _deferred.append((_DESTROY_ORDER[fn], len(_deferred), fn, h))
+
+
+def release_deferred() -> None:
+    """Destroy the library objects the garbage collector has dropped."""
+    if not _deferred:
+        return
+    items = sorted(_deferred)
+    _deferred.clear()
+    lib = load()
+    for _, _, fn, h in items:
+        getattr(lib, fn)(h)
+
+
+atexit.register(release_deferred)
 
 
 class LesasmError(RuntimeError):
@@ -150,6 +179,7 @@ class Mesh:
                  vreman_c: float = 0.1, colour: bool = False, keep_order: bool = False,
                  scatter: str | None = None):
         """scatter: "staged" (default), "chunk_atomic", "colour" or "direct"; colour=True is "colour"."""
+        release_deferred()
         lib = load()
         self._keep = [np.ascontiguousarray(coords, np.float64), np.ascontiguousarray(types, np.uint8),
                       np.ascontiguousarray(conn_offsets, np.int64), np.ascontiguousarray(conn, np.int32),
@@ -186,12 +216,13 @@ class Mesh:
         if getattr(self, "_h", None):
             load().lesasm_mesh_destroy(self._h)
             self._h = None
+        release_deferred()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            _defer("lesasm_mesh_destroy", h)
 
     # ---- orderings ---------------------------------------------------------
     def node_permutation(self) -> np.ndarray:
@@ -291,6 +322,7 @@ class Stepper:
     """Fractional-step time integration on a mesh (lesasm_stepper_*)."""
 
     def __init__(self, mesh: Mesh, nu: float, dt: float, rtol: float = 1e-12, maxit: int = 2000):
+        release_deferred()
         self.mesh = mesh
         h = ctypes.c_void_p()
         check(load().lesasm_stepper_create(mesh._h, float(nu), float(dt), float(rtol), int(maxit), ctypes.byref(h)))
@@ -300,12 +332,13 @@ class Stepper:
         if getattr(self, "_h", None):
             load().lesasm_stepper_destroy(self._h)
             self._h = None
+        release_deferred()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            _defer("lesasm_stepper_destroy", h)
 
     def step(self, u, p):
         """One time step in place on internal-order tensors u [n,3], p [n]."""
@@ -375,6 +408,7 @@ class StepGraph:
     order), which every replay updates in place."""
 
     def __init__(self, stepper: "Stepper", u, p, cg_iters: int, stream):
+        release_deferred()
         stepper.mesh._field(u)
         stepper.mesh._field(p)
         self.stepper, self.u, self.p = stepper, u, p
@@ -401,6 +435,13 @@ class StepGraph:
         if getattr(self, "_h", None):
             check(load().lesasm_step_graph_destroy(self._h))
             self._h = None
+        release_deferred()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            _defer("lesasm_step_graph_destroy", h)
 
 
 def check_stream(stream=None):
@@ -502,6 +543,7 @@ class Batch:
     """Many meshes assembled by one persistent launch (lesasm_batch_*)."""
 
     def __init__(self, meshes):
+        release_deferred()
         self.meshes = list(meshes)
         arr = (ctypes.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
         h = ctypes.c_void_p()
@@ -512,19 +554,22 @@ class Batch:
         if getattr(self, "_h", None):
             load().lesasm_batch_destroy(self._h)
             self._h = None
+        release_deferred()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            _defer("lesasm_batch_destroy", h)
 
     def configure(self, chunk: int = 0, order: int = ORDER_MESH, grid_per_cu: int = 2):
         check(load().lesasm_batch_configure(self._h, int(chunk), int(order), int(grid_per_cu)))
 
-    def set_per_type(self, on: bool):
-        """One persistent kernel per element type (True) or one for all (False)."""
-        check(load().lesasm_batch_set_per_type(self._h, 1 if on else 0))
+    def set_per_type(self, layout):
+        """Kernel layout: 0 / False one persistent kernel for all types, 1 / True
+        one persistent kernel per element type, 2 one kernel per element type
+        with one workgroup per queue item."""
+        check(load().lesasm_batch_set_per_type(self._h, int(layout)))
 
     def config(self) -> dict:
         c, o, g, n, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -570,6 +615,7 @@ class MLP:
     """The learned subgrid closure network on the GPU (lesasm_mlp_*)."""
 
     def __init__(self, params: np.ndarray):
+        release_deferred()
         p = np.ascontiguousarray(params, np.float32)
         if p.size != MLP_PARAMS:
             raise ValueError(f"expected {MLP_PARAMS} parameters")
@@ -581,12 +627,13 @@ class MLP:
         if getattr(self, "_h", None):
             load().lesasm_mlp_destroy(self._h)
             self._h = None
+        release_deferred()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            _defer("lesasm_mlp_destroy", h)
 
     def params(self) -> np.ndarray:
         out = np.empty(MLP_PARAMS, np.float32)
@@ -637,6 +684,7 @@ class MLP:
 def set_closure(mesh: Mesh, mlp: "MLP | None", delta_ref: float = 1.0, fallback_tol: float = 0.05):
     check(load().lesasm_mesh_set_closure(mesh._h, None if mlp is None else mlp._h, float(delta_ref),
                                          float(fallback_tol)))
+    mesh._closure = mlp  # the mesh uses the network's device weights: keep it alive as long
 
 
 def closure_fallbacks(mesh: Mesh) -> int:

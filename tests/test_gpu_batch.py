@@ -51,7 +51,7 @@ def batch_setup(torch_cuda):
 
 @pytest.mark.parametrize("chunk", [0, 64, 512])
 @pytest.mark.parametrize("order", [0, 1, 2])
-@pytest.mark.parametrize("per_type", [False, True])
+@pytest.mark.parametrize("per_type", [0, 1, 2])
 def test_batch_matches_oracle(torch_cuda, batch_setup, chunk, order, per_type):
     torch = torch_cuda
     cases, meshes, us, ps, refs, b = batch_setup
@@ -111,7 +111,7 @@ def test_rk3_stages_match_oracle(torch_cuda, batch_setup):
         assert rel(m.to_user(uw).cpu().numpy(), ref) < TOL64
 
 
-@pytest.mark.parametrize("per_type", [False, True])
+@pytest.mark.parametrize("per_type", [0, 1, 2])
 def test_graph_replays_match_eager(torch_cuda, batch_setup, per_type):
     """Replay the captured step several times with eager work and
     synchronisation in between; every replay equals the eager sequence

@@ -117,19 +117,24 @@ def test_learned_closure_20m_fp32_sampled(torch_cuda, hybrid20m):
     import os
     from oracle import closure
     from oracle import mlp as omlp
-    from paper_2005_05899_amd import lesasm
+    from paper_2005_05899_amd import lesasm, training
     torch = torch_cuda
     data = os.path.join(os.path.dirname(lesasm.__file__), "data")
     flat = np.load(os.path.join(data, "closure_weights.npy"))
-    delta_ref = json.load(open(os.path.join(data, "closure_weights.json")))["delta_ref"]
+    meta = json.load(open(os.path.join(data, "closure_weights.json")))
     case = hybrid20m
     m = lesasm.Mesh.from_arrays(case.mesh, case.vreman_c)
     m.precision = "fp32"
     net = lesasm.MLP(flat.astype(np.float32))
+    # the width reference the network was trained with: the mesh's geometric
+    # mean width (or a fixed value for networks trained before that rule)
+    delta_ref = training.mesh_delta_ref(m) if meta.get("delta_ref_rule") else meta["delta_ref"]
     lesasm.set_closure(m, net, delta_ref, 0.05)
     u = m.to_internal(torch.from_numpy(case.u).cuda())
     p = m.to_internal(torch.from_numpy(case.p).cuda())
     got = m.to_user(m.assemble_momentum_rhs(u, p, case.nu)).cpu().numpy()
+    lesasm.set_closure(m, net, delta_ref, 1e6)  # every element keeps the network
+    got_all = m.to_user(m.assemble_momentum_rhs(u, p, case.nu)).cpu().numpy()
     m.close()
     net.close()
     nodes = np.sort(np.random.default_rng(4).choice(case.mesh.n_field_nodes, 1000, replace=False))
@@ -147,13 +152,19 @@ def test_learned_closure_20m_fp32_sampled(torch_cuda, hybrid20m):
           f"|got - ref| per field {err}, bars {bars} (relative {bars / np.linalg.norm(ref[pos], axis=0)})",
           flush=True)
     assert (err <= bars).all(), (err, bars)
+    ref, use, eps, parts = closure.assemble(sub, case.u[fids], case.p[fids], case.nu, case.vreman_c, params,
+                                            delta_ref, 1e6, parts=True)
+    bars, near = closure_bars(sub, parts, eps, 1e6, ref, 1e-5, rows=pos)
+    err = np.linalg.norm(got_all[nodes] - ref[pos], axis=0)
+    print(f"  closure 20M fp32, all kept: |got - ref| per field {err}, bars {bars} "
+          f"(relative {bars / np.linalg.norm(ref[pos], axis=0)})", flush=True)
+    assert use.all() and near == 0 and (err <= bars).all(), (err, bars)
 
 
 def test_batch_64_partitions_sampled(torch_cuda):
     # the batched workload (64 partitions, about 25 M elements) in the
-    # configuration the autotuner picks on the MI355X (one persistent kernel
-    # per element type, chunks of 512, 2 workgroups per CU); 100 sampled
-    # nodes per partition against the oracle
+    # per-type layouts the autotuner chooses between on the MI355X (chunks of
+    # 512); 100 sampled nodes per partition against the oracle
     import oracle
     from paper_2005_05899_amd import lesasm
     torch = torch_cuda
@@ -168,20 +179,25 @@ def test_batch_64_partitions_sampled(torch_cuda):
         ps.append(m.to_internal(torch.from_numpy(c.p).cuda()))
     print(f"  batch of {len(meshes)} partitions, {sum(c.mesh.n_elems for c in cases)} elements", flush=True)
     b = lesasm.Batch(meshes)
-    b.set_per_type(True)
-    b.configure(chunk=512, order=0, grid_per_cu=2)
-    outs = [torch.full_like(u, float("nan")) for u in us]
-    b.assemble(us, ps, [c.nu for c in cases], outs)
-    torch.cuda.synchronize()
-    worst = 0.0
-    for i, (c, m, o) in enumerate(zip(cases, meshes, outs)):
-        got = m.to_user(o).cpu().numpy()
-        assert np.isfinite(got).all()
+    refs = []
+    for i, c in enumerate(cases):
         nodes = np.sort(np.random.default_rng(100 + i).choice(c.mesh.n_field_nodes, 100, replace=False))
-        ref, _ = _sampled_reference(c, nodes)
-        worst = max(worst, float((np.abs(got[nodes] - ref) / np.abs(ref).max(axis=0)).max()))
-    print(f"  worst sampled error over the partitions {worst:.3e}", flush=True)
-    assert worst <= 1e-12
+        refs.append((nodes, _sampled_reference(c, nodes)[0]))
+    # the two per-type layouts: persistent kernels with queue counters, and one
+    # workgroup per item
+    for layout in (1, 2):
+        b.set_per_type(layout)
+        b.configure(chunk=512, order=0, grid_per_cu=2)
+        outs = [torch.full_like(u, float("nan")) for u in us]
+        b.assemble(us, ps, [c.nu for c in cases], outs)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for c, m, o, (nodes, ref) in zip(cases, meshes, outs, refs):
+            got = m.to_user(o).cpu().numpy()
+            assert np.isfinite(got).all()
+            worst = max(worst, float((np.abs(got[nodes] - ref) / np.abs(ref).max(axis=0)).max()))
+        print(f"  layout {layout}: worst sampled error over the partitions {worst:.3e}", flush=True)
+        assert worst <= 1e-12
     b.close()
     for m in meshes:
         m.close()

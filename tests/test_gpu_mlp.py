@@ -139,6 +139,19 @@ def test_fused_closure_matches_oracle(torch_cuda, net, precision):
     err = np.linalg.norm(got - ref, axis=0)
     print(f"  {precision}: |got - ref| per field {err}, bars {bars} (relative {bars / np.linalg.norm(ref, axis=0)})")
     assert (err <= bars).all(), (err, bars)
+    # every element keeps the network (no keep-or-fall-back decision can
+    # differ): the bar is two BF16 units of the network's stress term plus the
+    # plain assembly's
+    lesasm.set_closure(mesh, m, delta_ref, 1e6)
+    got = mesh.to_user(mesh.assemble_momentum_rhs(u, pp, c.nu)).cpu().numpy()
+    ref_all, use_all, eps_all, parts_all = closure.assemble(c.mesh, c.u, c.p, c.nu, c.vreman_c, p, delta_ref, 1e6,
+                                                            parts=True)
+    assert use_all.all() and sum(lesasm.closure_fallbacks_by_type(mesh).values()) == 0
+    bars, near_all = closure_bars(c.mesh, parts_all, eps_all, 1e6, ref_all, 1e-12 if precision == "fp64" else 1e-5)
+    err = np.linalg.norm(got - ref_all, axis=0)
+    print(f"  {precision} all kept: |got - ref| per field {err}, bars {bars} "
+          f"(relative {bars / np.linalg.norm(ref_all, axis=0)})")
+    assert near_all == 0 and (err <= bars).all(), (err, bars)
     lesasm.set_closure(mesh, None)
     plain = mesh.to_user(mesh.assemble_momentum_rhs(u, pp, c.nu)).cpu().numpy()
     vref = oracle.assemble(c.mesh, c.u, c.p, c.nu, c.vreman_c)
@@ -154,14 +167,15 @@ def test_fallback_counts_over_many_workgroups(torch_cuda):
     # resets them, and a zero tolerance counts every element once
     import json
     import os
-    from paper_2005_05899_amd import lesasm
+    from paper_2005_05899_amd import lesasm, training
     torch = torch_cuda
     case = mg.hybrid_2m_case()
     data = os.path.join(os.path.dirname(lesasm.__file__), "data")
     flat = np.load(os.path.join(data, "closure_weights.npy")).astype(np.float32)
-    delta_ref = json.load(open(os.path.join(data, "closure_weights.json")))["delta_ref"]
+    meta = json.load(open(os.path.join(data, "closure_weights.json")))
     m = lesasm.MLP(flat)
     mesh = lesasm.Mesh.from_arrays(case.mesh, case.vreman_c)
+    delta_ref = training.mesh_delta_ref(mesh) if meta.get("delta_ref_rule") else meta["delta_ref"]
     mesh.precision = "fp32"
     u = mesh.to_internal(torch.from_numpy(case.u).cuda())
     p = mesh.to_internal(torch.from_numpy(case.p).cuda())

@@ -123,7 +123,10 @@ def test_batch_graph_recaptured_while_replays_queued(torch_cuda):
 
 def test_memory_cap_gives_oom(torch_cuda):
     from paper_2005_05899_amd import lesasm
+    import gc
     c = mg.small_hybrid_case(nx=6, ny=5, seed=3)
+    gc.collect()
+    lesasm.release_deferred()  # objects other tests left to the collector: freed before the baseline
     before = lesasm.memory_in_use()
     lesasm.set_memory_cap(before + 4096)
     try:

@@ -1,10 +1,17 @@
 """The learned closure end to end at small scale: decaying turbulence run by
-this library's solver, box-filtered samples, training with the GPU kernels,
-and the a-priori gain over the method without it on a held-out snapshot.
+this library's solver, box-filtered samples (on the filtered grid's own cells
+and on the Gauss points of graded, perturbed hybrid boxes at the same
+spacing), training with the GPU kernels, and the a-priori gain over the method
+without it on a held-out snapshot.
 
-Pass criteria: the trained network's subgrid stress is closer to the
-filtered-DNS stress than Vreman's (relative L2, Frobenius) and than no model
-at all, and correlates better with it.
+Pass criteria, on all held-out samples, on the grid samples and on the
+hybrid-element samples: the trained network's subgrid stress is closer to the
+filtered-DNS stress than Vreman's (relative L2, Frobenius) and correlates
+better with it; on all samples and on the hybrid ones it is also closer than no
+model at all.  (The grid samples of this small case, the 32^3 and 16^3 cells
+of three snapshots, are too few for that last margin to be stable; the
+committed network, trained on 128^3 data, is 0.74 against no model's 1.00
+there.)
 """
 import numpy as np
 import pytest
@@ -22,22 +29,19 @@ def torch_cuda():
 
 def test_trained_closure_beats_vreman_a_priori(torch_cuda):
     from paper_2005_05899_amd import training as tr
-    torch = torch_cuda
-    snaps, times = tr.decaying_turbulence(n=48, nu=0.01, dt=0.01, steps=60, snap_every=10, first_snap=30)
+    snaps, times = tr.decaying_turbulence(n=64, nu=0.01, dt=0.01, steps=60, snap_every=10, first_snap=30)
     assert len(snaps) == 4 and all(np.isfinite(s).all() for s in snaps)
-    datas, delta_ref = [], None
-    for s in snaps[:-1]:
-        d, delta_ref = tr.samples_from_snapshot(s, delta_ref=delta_ref)
-        datas.append(d)
-    data = {k: np.concatenate([d[k] for d in datas]) for k in datas[0]}
-    params, hist, net = tr.train(data["x"], data["t"], steps=800, batch=4096, lr=2e-3)
+    data, delta_ref = tr.gathered_samples(snaps[:-1], seed0=11)
+    assert data["hybrid"].any() and (~data["hybrid"]).any()
+    params, hist, net = tr.train(data["x"], data["t"], steps=1500, batch=4096, lr=2e-3, weights=data["w"])
     assert hist[-1][1] < 0.5 * hist[0][1]
-    test, _ = tr.samples_from_snapshot(snaps[-1], delta_ref=delta_ref)
-    y = net.infer_bf16(torch.from_numpy(test["x"]).cuda()).cpu().numpy().astype(np.float64)
-    tau = (test["delta"] ** 2 * (test["G"].reshape(-1, 9) ** 2).sum(axis=1))[:, None] * tr.deviatoric(y)
-    rep = tr.apriori_errors(tau, test)
-    print(f"  a-priori on held-out t={times[-1]:.2f}: {rep}", flush=True)
-    assert rep["mlp_rel_err"] < rep["vreman_rel_err"]
-    assert rep["mlp_rel_err"] < rep["zero_rel_err"]
-    assert rep["mlp_corr"] > rep["vreman_corr"]
+    test, _ = tr.gathered_samples(snaps[-1:], seed0=21, delta_ref=delta_ref)
+    rep = tr.apriori_report(net, test)
+    for k, r in rep.items():
+        print(f"  a-priori on held-out t={times[-1]:.2f}, {k}: {r}", flush=True)
+    for k in ("all", "grid", "hybrid"):
+        assert rep[k]["mlp_rel_err"] < rep[k]["vreman_rel_err"], k
+        assert rep[k]["mlp_corr"] > rep[k]["vreman_corr"], k
+    for k in ("all", "hybrid"):
+        assert rep[k]["mlp_rel_err"] < rep[k]["zero_rel_err"], k
     net.close()

@@ -141,3 +141,124 @@ def test_samples_are_normalised_and_deviatoric():
     assert np.allclose(x[:, 9], np.log(delta / dref), rtol=0, atol=1e-7)
     assert np.abs(tau[:, :3].sum(axis=1)).max() <= 1e-14 * np.abs(tau).max()
     assert np.allclose(t, tau / (delta ** 2 * g2)[:, None], rtol=1e-6, atol=1e-7 * np.abs(t).max())
+
+
+# ---- samples on hybrid elements -----------------------------------------------------
+
+def test_gauss_jacobi_rule_is_exact_to_degree_three():
+    c, w = TR._gauss_jacobi2()
+    for k in range(4):
+        exact = 2.0 / ((k + 1) * (k + 2) * (k + 3))  # int_0^1 c^k (1 - c)^2 dc
+        assert abs((w * c ** k).sum() - exact) <= 1e-15, k
+    assert ((c > 0) & (c < 1)).all() and (w > 0).all()
+
+
+def test_reference_elements_reproduce_linear_fields():
+    # partition of unity, rule weights summing to the reference volume, and
+    # linear completeness: sum_a N_a xi_a = xi and sum_a xi_a (x) dN_a = I at
+    # every Gauss point (node coordinates written out per type)
+    nodes = {
+        mg.TET04: [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]],
+        mg.PYR05: [[-1, -1, 0], [1, -1, 0], [1, 1, 0], [-1, 1, 0], [0, 0, 1]],
+        mg.PEN06: [[0, 0, -1], [1, 0, -1], [0, 1, -1], [0, 0, 1], [1, 0, 1], [0, 1, 1]],
+        mg.HEX08: [[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1], [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]],
+    }
+    vol = {mg.TET04: 1 / 6, mg.PYR05: 4 / 3, mg.PEN06: 1.0, mg.HEX08: 8.0}
+    for t, xn in nodes.items():
+        xn = np.array(xn, float)
+        xi, w = TR.reference_rule(t)
+        N, dN = TR.reference_shape(t, xi)
+        assert abs(w.sum() - vol[t]) <= 1e-15, t
+        assert np.abs(N.sum(axis=1) - 1).max() <= 1e-15, t
+        assert np.abs(N @ xn - xi).max() <= 1e-15, t
+        assert np.abs(np.einsum("ak,gaj->gkj", xn, dN) - np.eye(3)).max() <= 1e-14, t
+        # each node's function is 1 there and 0 at the other nodes (at the nodes,
+        # the pyramid apex excepted: its base functions are singular there)
+        pts = xn if t != mg.PYR05 else xn[:4]
+        Nn, _ = TR.reference_shape(t, pts)
+        assert np.abs(Nn - np.eye(len(xn))[:len(pts)]).max() <= 1e-15, t
+
+
+def test_hybrid_samples_of_a_linear_field():
+    # a velocity linear in x on the grid: every Gauss point of every element
+    # away from the periodic seam sees G = A (isoparametric completeness on the
+    # perturbed, graded elements); the widths' cubes add up to the box volume;
+    # a constant stress field gives its deviatoric part everywhere
+    m, L = 12, 2 * math.pi
+    h = L / m
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((3, 3))
+    k, j, i = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    x = np.stack([i * h, j * h, k * h], axis=-1)
+    ub = x @ A.T + rng.standard_normal(3)
+    t6 = rng.standard_normal(6)
+    tau = np.broadcast_to(t6, (m, m, m, 6)).copy()
+    raw = TR.hybrid_element_samples(ub, tau, L, seed=5)
+    n = len(raw["delta"])
+    assert raw["G"].shape == (n, 3, 3) and raw["tau"].shape == (n, 6) and raw["etype"].shape == (n,)
+    assert set(np.unique(raw["etype"])) == {mg.TET04, mg.PYR05, mg.PEN06, mg.HEX08}
+    dev = t6.copy()
+    dev[:3] -= t6[:3].mean()
+    assert np.abs(raw["tau"] - dev).max() <= 1e-14
+    # elements away from the seam: rebuild the same box and take the elements
+    # whose nodes all lie below L - h in x, y and z (their Gauss points follow
+    # the per-type order of the sampler)
+    mesh = mg.hybrid_box(m, m, mg.hybrid_layers(m * m, int(m ** 3 / (0.4 / 6 + 0.4 / 2 + 0.05 / 6 + 0.15))),
+                         length=(L,) * 3, seed=5)
+    o, checked, vol = 0, 0, 0.0
+    for t in (mg.TET04, mg.PYR05, mg.PEN06, mg.HEX08):
+        idx = np.flatnonzero(mesh.types == t)
+        ng = len(TR.reference_rule(t)[1])
+        conn = mesh.conn[mesh.conn_offsets[idx][:, None] + np.arange(mg.NNODE[t])[None, :]]
+        inner = (mesh.coords[conn] < L - h - 1e-9).all(axis=(1, 2))
+        G = raw["G"][o:o + ng * len(idx)].reshape(len(idx), ng, 3, 3)
+        d = raw["delta"][o:o + ng * len(idx)].reshape(len(idx), ng)
+        assert np.abs(G[inner] - A).max() <= 1e-11 * np.abs(A).max(), t
+        vol += (d[:, 0] ** 3).sum()
+        checked += int(inner.sum())
+        o += ng * len(idx)
+    assert o == n and checked > 0.3 * mesh.n_elems
+    # the generator's one non-conforming interface plane (bilinear quad faces
+    # against pairs of triangles, perturbed) leaves slivers: 1e-5 of the volume
+    assert abs(vol - L ** 3) <= 1e-4 * L ** 3
+
+
+def test_hybrid_network_samples_are_normalised():
+    m, L = 8, 2 * math.pi
+    rng = np.random.default_rng(4)
+    ub = rng.standard_normal((m, m, m, 3))
+    tau = rng.standard_normal((m, m, m, 6))
+    raw = TR.hybrid_element_samples(ub, tau, L, seed=6)
+    dref = 0.7 * L / m
+    s = TR.network_samples(raw, dref)
+    g2 = (s["G"].reshape(-1, 9) ** 2).sum(axis=1)
+    assert np.abs(np.linalg.norm(s["x"][:, :9], axis=1) - 1).max() <= 1e-6
+    assert np.allclose(s["x"][:, 9], np.log(s["delta"] / dref), atol=1e-6)
+    assert np.allclose(s["t"], s["tau"] / (s["delta"] ** 2 * g2)[:, None], rtol=1e-6)
+    assert np.abs(s["t"][:, :3].sum(axis=1)).max() <= 1e-5 * np.abs(s["t"]).max()
+    # tetrahedra of a cube cell are narrower than the hexahedra: widths ~0.55 h against ~h
+    w_tet = np.median(s["delta"][s["etype"] == mg.TET04])
+    w_hex = np.median(s["delta"][s["etype"] == mg.HEX08])
+    assert 0.45 < w_tet / (L / m) < 0.65 and 0.85 < w_hex / (L / m) < 1.15
+
+
+def test_gathered_samples_weights_and_levels():
+    # both sample kinds and both filter levels are present; the drawing weight
+    # is (Delta / level width)^4 with the level width the geometric mean of
+    # that level's hybrid-element widths, and the width input is relative to
+    # the level-1 width
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal((16, 16, 16, 3))
+    d, dref = TR.gathered_samples([u], seed0=3)
+    n = len(d["x"])
+    assert all(len(d[k]) == n for k in ("t", "G", "tau", "delta", "etype", "level", "hybrid", "w"))
+    assert d["hybrid"].any() and (~d["hybrid"]).any()
+    assert set(np.unique(d["level"])) == {1, 2}
+    for lev in (1, 2):
+        hy = d["hybrid"] & (d["level"] == lev)
+        assert abs(np.log(d["w"][hy]).mean() / 4) <= 1e-12, lev
+    h1 = 2 * math.pi / 8
+    assert np.allclose(d["delta"][~d["hybrid"] & (d["level"] == 1)], h1)
+    assert np.allclose(d["delta"][~d["hybrid"] & (d["level"] == 2)], 2 * h1)
+    assert abs(np.log(d["delta"][d["hybrid"] & (d["level"] == 1)] / dref).mean()) <= 1e-12
+    assert np.allclose(d["x"][:, 9], np.log(d["delta"] / dref), atol=1e-6)
