@@ -404,6 +404,17 @@ int lesasm_mlp_set_params(lesasm_mlp *mlp, const float *params);
  * lesasm_mlp_commit to refresh the BF16 inference copy (synchronises). */
 int lesasm_mlp_loss_grad(lesasm_mlp *mlp, const float *d_x, const float *d_t, int n, float *d_grad, float *d_loss,
                          void *stream);
+/* lesasm_mlp_loss_grad without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results (bit for bit)
+ * as lesasm_mlp_loss_grad, but the work arrays sit in a static device area of
+ * 8192 samples (8.6 MB, held by each device the library runs on until the
+ * process ends): n > 8192 gives LESASM_E_INVALID_ARG and nothing runs.  The
+ * area's address is looked up on the first call on each device.  Every call
+ * on one device shares that area: calls that overlap on one device (two
+ * streams, or two threads) race and must be ordered by the caller. */
+int lesasm_mlp_loss_grad_noalloc(lesasm_mlp *mlp, const float *d_x, const float *d_t, int n, float *d_grad,
+                                 float *d_loss, void *stream);
 int lesasm_mlp_adam(lesasm_mlp *mlp, const float *d_grad, float lr, void *stream);
 int lesasm_mlp_train_step(lesasm_mlp *mlp, const float *d_x, const float *d_t, int n, float lr, float *d_loss,
                           void *stream);

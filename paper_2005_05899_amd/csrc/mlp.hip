@@ -9,6 +9,8 @@
 // eps 1e-8.  Every reduction over samples runs in a fixed order.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "mlp.hpp"
 
@@ -335,6 +337,66 @@ extern "C" int lesasm_mlp_loss_grad(lesasm_mlp *p, const float *d_x, const float
     hipLaunchKernelGGL(k_mlp_wgrad, dim3(141), dim3(64), 0, s, d_x, p->H1, p->H2, p->DA1, p->DA2, p->DY, n,
                        d_grad ? d_grad : p->grad);
     if (d_loss) hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(256), 0, s, p->loss, n, d_loss);
+    LESASM_HIP_TRY(hipGetLastError());
+    return LESASM_OK;
+}
+
+// ---- loss gradient without allocation -------------------------------------------
+// The training work arrays of lesasm_mlp_loss_grad_noalloc live in one
+// file-scope device array, H1, H2, DA1, DA2 [n][64], DY [n][6], loss [n] for
+// n up to kNoAllocMaxSamples (8.6 MB; each device holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: its
+// device address is taken once per device with hipGetSymbolAddress and kept
+// in g_scratch.  Every kernel writes each work entry of samples < n before
+// any kernel reads it, so nothing is cleared between calls.
+namespace {
+constexpr int kNoAllocMaxSamples = 8192;
+constexpr size_t kScratchPerSample = 4 * kMlpH + kMlpOut + 1;
+constexpr int kScratchDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) float scratch[(size_t)kNoAllocMaxSamples * kScratchPerSample];
+
+static std::mutex g_scratch_mu;
+static float *g_scratch[kScratchDevices];
+
+static int scratch_address(int device, float **out) {
+    if (device < 0 || device >= kScratchDevices)
+        return fail(LESASM_E_UNSUPPORTED, "mlp_loss_grad_noalloc: device id too large");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LESASM_E_HIP, std::string("mlp_loss_grad_noalloc: hipGetSymbolAddress failed: ") +
+                                          hipGetErrorString(e));
+        g_scratch[device] = (float *)ptr;
+    }
+    *out = g_scratch[device];
+    return LESASM_OK;
+}
+
+extern "C" int lesasm_mlp_loss_grad_noalloc(lesasm_mlp *p, const float *d_x, const float *d_t, int n,
+                                            float *d_grad, float *d_loss, void *stream) {
+    if (!p || !d_x || !d_t || n < 1) return fail(LESASM_E_INVALID_ARG, "mlp_loss_grad_noalloc: bad argument");
+    if (n > kNoAllocMaxSamples)
+        return fail(LESASM_E_INVALID_ARG, "mlp_loss_grad_noalloc: n = " + std::to_string(n) + " exceeds the " +
+                                              std::to_string(kNoAllocMaxSamples) + " samples of the static work area");
+    int dev = -1;
+    LESASM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device) return fail(LESASM_E_STATE, "mlp_loss_grad_noalloc: current device differs from the mlp's");
+    float *w = nullptr;
+    int st = scratch_address(dev, &w);
+    if (st) return st;
+    const size_t N = (size_t)n;
+    float *H1 = w, *H2 = H1 + N * kMlpH, *DA1 = H2 + N * kMlpH, *DA2 = DA1 + N * kMlpH, *DY = DA2 + N * kMlpH,
+          *loss = DY + N * kMlpOut;
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 g((n + 127) / 128), b(128);
+    hipLaunchKernelGGL(k_mlp_fwd_train, g, b, 0, s, p->params, d_x, d_t, n, H1, H2, DY, loss);
+    hipLaunchKernelGGL(k_mlp_bwd_act, g, b, 0, s, p->params, H1, H2, DY, n, DA1, DA2);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(141), dim3(64), 0, s, d_x, H1, H2, DA1, DA2, DY, n, d_grad ? d_grad : p->grad);
+    if (d_loss) hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(256), 0, s, loss, n, d_loss);
     LESASM_HIP_TRY(hipGetLastError());
     return LESASM_OK;
 }

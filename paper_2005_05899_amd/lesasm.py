@@ -44,7 +44,7 @@ EXPORTS = [
     "lesasm_element_centroids", "lesasm_sfc_workspace_bytes", "lesasm_sfc_partition", "lesasm_balance_update",
     "lesasm_batch_set_per_type", "lesasm_batch_get_per_type",
     "lesasm_step_graph_create", "lesasm_step_graph_launch", "lesasm_step_graph_stats", "lesasm_step_graph_destroy",
-    "lesasm_set_memory_cap", "lesasm_memory_in_use",
+    "lesasm_set_memory_cap", "lesasm_memory_in_use", "lesasm_mlp_loss_grad_noalloc",
 ]
 MLP_PARAMS = 5254
 ORDER_MESH, ORDER_LARGEST_FIRST, ORDER_INTERLEAVED = 0, 1, 2
@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
         "lesasm_batch_rk3_launch": [P, P], "lesasm_batch_rk3_eager": [P, P, P, P, D, P],
         "lesasm_mlp_create": [P, P], "lesasm_mlp_destroy": [P], "lesasm_mlp_get_params": [P, P],
         "lesasm_mlp_set_params": [P, P], "lesasm_mlp_loss_grad": [P, P, P, I, P, P, P],
+        "lesasm_mlp_loss_grad_noalloc": [P, P, P, I, P, P, P],
         "lesasm_mlp_adam": [P, P, ctypes.c_float, P], "lesasm_mlp_train_step": [P, P, P, I, ctypes.c_float, P, P],
         "lesasm_mlp_commit": [P], "lesasm_mlp_forward_f32": [P, P, I, P, P], "lesasm_mlp_infer_bf16": [P, P, I, P, P],
         "lesasm_mesh_set_closure": [P, P, D, D], "lesasm_mesh_closure_fallbacks": [P, P],
@@ -656,6 +657,13 @@ class MLP:
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
         check(load().lesasm_mlp_loss_grad(self._h, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream()))
         return loss, g
+
+    def loss_grad_noalloc(self, x, t, grad, loss):
+        """loss_grad into caller buffers with no device allocation by the
+        library (at most 8192 samples)."""
+        self._f32(x, 10), self._f32(t, 6)
+        check(load().lesasm_mlp_loss_grad_noalloc(self._h, _ptr(x), _ptr(t), x.shape[0], _ptr(grad), _ptr(loss),
+                                                  _stream()))
 
     def adam(self, grad=None, lr: float = 1e-3):
         check(load().lesasm_mlp_adam(self._h, _ptr(grad), ctypes.c_float(lr), _stream()))
