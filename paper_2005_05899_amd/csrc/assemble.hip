@@ -224,10 +224,21 @@ bool mesh_is_staged(const lesasm_mesh *m) {
     return mesh_is_chunked(m) && !(m->flags & LESASM_MESH_SCATTER_CHUNK_ATOMIC);
 }
 
+// Gather of the staged rows of shared-node class cls (see gather_off) on s.
+static void launch_gather(lesasm_mesh *m, int cls, double *rhs, hipStream_t s) {
+    const int a = m->gather_off[cls], n = m->gather_off[cls + 1] - a;
+    if (n <= 0) return;
+    ProfileScope ps(m, LESASM_KERNEL_GATHER, s);
+    hipLaunchKernelGGL(k_gather_shared, dim3((n + 255) / 256), dim3(256), 0, s, m->d_gnode + a, m->d_goffs + a,
+                       m->d_stage, rhs, n);
+}
+
 // Chunked scatters: the type kernels run concurrently, the first on the
-// caller's stream and the others on the mesh's side streams (fork and join
-// through events, so the sequence can be captured in a graph), followed by
-// the gather of staged rows on the caller's stream.
+// caller's stream and the others on the device's side streams (fork and join
+// through events, so the sequence can be captured in a graph).  Staged: the
+// shared nodes whose rows come from one type only are gathered on that type's
+// stream right after its kernel (the memory-bound gather overlaps the other
+// types' arithmetic), the rest on the caller's stream after the join.
 static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
     const bool staged = mesh_is_staged(m);
     ClosureView clv{};
@@ -254,32 +265,31 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
             if (used <= 3) LESASM_HIP_TRY(hipStreamWaitEvent(sk, m->ev_fork, 0));
         }
         ++used;
-        ProfileScope ps(m, LESASM_KERNEL_TET04 + k, sk);
-        ClosureView clk{};
-        if (cl) {  // fallback counters of this category
-            clk = clv;
-            clk.fallbacks = m->d_fallbacks + (size_t)k * kFallbackSlots;
-            cl = &clk;
+        {
+            ProfileScope ps(m, LESASM_KERNEL_TET04 + k, sk);
+            ClosureView clk{};
+            if (cl) {  // fallback counters of this category
+                clk = clv;
+                clk.fallbacks = m->d_fallbacks + (size_t)k * kFallbackSlots;
+                cl = &clk;
+            }
+            const bool periodic = c.d_lf != c.d_lg;
+            const bool f32 = m->precision == LESASM_PREC_FP32;
+            if (staged) {
+                if (f32) dispatch_chunks<float, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+                else dispatch_chunks<double, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            } else {
+                if (f32) dispatch_chunks<float, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+                else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
+            }
         }
-        const bool periodic = c.d_lf != c.d_lg;
-        const bool f32 = m->precision == LESASM_PREC_FP32;
-        if (staged) {
-            if (f32) dispatch_chunks<float, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else dispatch_chunks<double, true>(c, m->d_stage, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-        } else {
-            if (f32) dispatch_chunks<float, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-            else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
-        }
+        if (staged) launch_gather(m, k, rhs, sk);
     }
     for (int i = 0; i < (m->concurrent ? std::min(used - 1, 3) : 0); ++i) {
         LESASM_HIP_TRY(hipEventRecord(m->ev_join[i], m->side[i]));
         LESASM_HIP_TRY(hipStreamWaitEvent(s, m->ev_join[i], 0));
     }
-    if (staged && m->n_gather > 0) {
-        ProfileScope ps(m, LESASM_KERNEL_GATHER, s);
-        hipLaunchKernelGGL(k_gather_shared, dim3((m->n_gather + 255) / 256), dim3(256), 0, s, m->d_gnode, m->d_goffs,
-                           m->d_stage, rhs, m->n_gather);
-    }
+    if (staged) launch_gather(m, kNumCat, rhs, s);
     LESASM_HIP_TRY(hipGetLastError());
     return LESASM_OK;
 }

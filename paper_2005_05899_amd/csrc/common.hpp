@@ -167,6 +167,12 @@ struct lesasm_mesh {
     int32_t n_gather = 0;           // field nodes owned by no chunk
     int32_t *d_gnode = nullptr;     // [n_gather] their ids
     int32_t *d_goffs = nullptr;     // [n_gather+1] first staging row of each shared node (rows consecutive)
+    // the shared nodes grouped by the categories whose chunks wrote their rows:
+    // class k < kNumCat holds rows of category k only (gathered on that
+    // category's stream right after its kernel), class kNumCat the rest
+    // (several categories, or no element), gathered after the join;
+    // class c is [gather_off[c], gather_off[c+1]) of d_gnode
+    int32_t gather_off[lesasm::kNumCat + 2] = {0};
     // side streams and events running the four type kernels concurrently
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     // learned closure (NULL: Vreman)

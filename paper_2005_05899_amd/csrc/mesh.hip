@@ -375,9 +375,13 @@ static int build_staging(lesasm_mesh *m) {
     dfree(m, m->d_goffs);
     m->n_slots = 0;
     m->n_gather = 0;
-    // Rows of one shared node are consecutive (node order, then type and chunk
-    // order), so the gather reads them without an index array.
+    for (int g = 0; g < kNumCat + 2; ++g) m->gather_off[g] = 0;
+    // Rows of one shared node are consecutive (type and chunk order), so the
+    // gather reads them without an index array.  Shared nodes are grouped by
+    // the categories that wrote their rows (class k: category k only, class
+    // kNumCat: several, or none), node order inside a class.
     std::vector<int32_t> owned(m->n_field, 0), count(m->n_field, 0);
+    std::vector<uint8_t> cats(m->n_field, 0);
     int64_t total = 0;
     for (int k = 0; k < kNumCat; ++k) {
         const Category &c = m->cat[k];
@@ -388,18 +392,27 @@ static int build_staging(lesasm_mesh *m) {
             else {
                 count[f]++;
                 total++;
+                cats[f] |= (uint8_t)(1u << k);
             }
         }
     }
     if (total >= INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "mesh_create: too many staging rows");
+    std::vector<uint8_t> cls(m->n_field, (uint8_t)kNumCat);
+    for (int64_t f = 0; f < m->n_field; ++f)
+        for (int k = 0; k < kNumCat; ++k)
+            if (cats[f] == (1u << k)) cls[f] = (uint8_t)k;
     std::vector<int32_t> gnode, goffs{0};
     std::vector<int32_t> pos(m->n_field, -1);
-    for (int64_t f = 0; f < m->n_field; ++f)
-        if (!owned[f]) {  // includes nodes of no element (count 0): the gather writes their zero
-            pos[f] = goffs.back();
-            gnode.push_back((int32_t)f);
-            goffs.push_back(goffs.back() + count[f]);
-        }
+    m->gather_off[0] = 0;
+    for (int g = 0; g <= kNumCat; ++g) {
+        for (int64_t f = 0; f < m->n_field; ++f)
+            if (!owned[f] && cls[f] == g) {  // includes nodes of no element (count 0): the gather writes their zero
+                pos[f] = goffs.back();
+                gnode.push_back((int32_t)f);
+                goffs.push_back(goffs.back() + count[f]);
+            }
+        m->gather_off[g + 1] = (int32_t)gnode.size();
+    }
     std::vector<std::vector<int32_t>> fslot(kNumCat);
     for (int k = 0; k < kNumCat; ++k) {
         Category &c = m->cat[k];
