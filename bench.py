@@ -616,6 +616,36 @@ def run_precision(args):
                       "u": uu, "p": pp}
         st.close()
         print(f"  step {prec}: {step[prec]['ms']:.1f} ms, {it} CG iterations", file=sys.stderr, flush=True)
+    # the same step (FP64) from the step graph: stages, divergence, the CG with
+    # the eager step's iteration count plus a margin captured (iterations after
+    # convergence return at once on the device), correction; one replay to warm
+    # up, then one timed replay from the same state
+    mesh.precision = "fp64"
+    st = lesasm.Stepper(mesh, case.nu, dt, rtol=1e-10, maxit=20000)
+    gs = torch.cuda.Stream()
+    ug, pg = u.clone(), p.clone()
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    g = lesasm.StepGraph(st, ug, pg, step["fp64"]["cg_iterations"] + 64, gs)
+    t_capture = time.perf_counter() - tc
+    g.launch(gs)
+    gs.synchronize()
+    ug.copy_(u)
+    pg.copy_(p)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    g.launch(gs)
+    gs.synchronize()
+    t_graph = time.perf_counter() - ts
+    it_g, res_g, ok_g = g.stats()
+    step["fp64_step_graph"] = {"ms": 1e3 * t_graph, "cg_iterations": it_g, "cg_relative_residual": res_g,
+                               "converged": ok_g, "captured_cg_iterations": step["fp64"]["cg_iterations"] + 64,
+                               "capture_and_instantiate_s": t_capture,
+                               "velocity_vs_eager": field_errors(mesh.to_user(ug).cpu().numpy(),
+                                                                 mesh.to_user(step["fp64"]["u"]).cpu().numpy())}
+    print(f"  step graph fp64: {1e3 * t_graph:.1f} ms, {it_g} CG iterations", file=sys.stderr, flush=True)
+    g.close()
+    st.close()
     # the pressure CG alone: a fixed number of iterations on this mesh's Laplacian
     st = lesasm.Stepper(mesh, case.nu, dt, rtol=1e-30, maxit=300)
     b = lesasm.divergence(mesh, u)

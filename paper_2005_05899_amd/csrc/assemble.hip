@@ -224,9 +224,14 @@ bool mesh_is_staged(const lesasm_mesh *m) {
     return mesh_is_chunked(m) && !(m->flags & LESASM_MESH_SCATTER_CHUNK_ATOMIC);
 }
 
-// Gather of the staged rows of shared-node class cls (see gather_off) on s.
-static void launch_gather(lesasm_mesh *m, int cls, double *rhs, hipStream_t s) {
-    const int a = m->gather_off[cls], n = m->gather_off[cls + 1] - a;
+// Shared nodes from which on the gather is split by class: below, one launch
+// after the join (the overlap of a few microseconds would not pay for the
+// extra launches of a small mesh).
+constexpr int kSplitGather = 1 << 18;
+
+// Gather of the staged rows of shared-node classes [c0, c1) (see gather_off) on s.
+static void launch_gather(lesasm_mesh *m, int c0, int c1, double *rhs, hipStream_t s) {
+    const int a = m->gather_off[c0], n = m->gather_off[c1] - a;
     if (n <= 0) return;
     ProfileScope ps(m, LESASM_KERNEL_GATHER, s);
     hipLaunchKernelGGL(k_gather_shared, dim3((n + 255) / 256), dim3(256), 0, s, m->d_gnode + a, m->d_goffs + a,
@@ -235,10 +240,11 @@ static void launch_gather(lesasm_mesh *m, int cls, double *rhs, hipStream_t s) {
 
 // Chunked scatters: the type kernels run concurrently, the first on the
 // caller's stream and the others on the device's side streams (fork and join
-// through events, so the sequence can be captured in a graph).  Staged: the
-// shared nodes whose rows come from one type only are gathered on that type's
-// stream right after its kernel (the memory-bound gather overlaps the other
-// types' arithmetic), the rest on the caller's stream after the join.
+// through events, so the sequence can be captured in a graph).  Staged, with
+// at least kSplitGather shared nodes: the shared nodes whose rows come from one
+// type only are gathered on that type's stream right after its kernel (the
+// memory-bound gather overlaps the other types' arithmetic), the rest on the
+// caller's stream after the join; fewer: all of them after the join.
 static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, double nu, double *rhs, hipStream_t s) {
     const bool staged = mesh_is_staged(m);
     ClosureView clv{};
@@ -283,13 +289,13 @@ static int launch_chunked(lesasm_mesh *m, const double *u, const double *p, doub
                 else dispatch_chunks<double, false>(c, nullptr, cl, p != nullptr, periodic, m->block, m->persist == 1 ? m->n_cu : -m->persist, sk, m->d_xyz, u, p, nu, m->vreman_c, rhs);
             }
         }
-        if (staged) launch_gather(m, k, rhs, sk);
+        if (staged && m->n_gather >= kSplitGather) launch_gather(m, k, k + 1, rhs, sk);
     }
     for (int i = 0; i < (m->concurrent ? std::min(used - 1, 3) : 0); ++i) {
         LESASM_HIP_TRY(hipEventRecord(m->ev_join[i], m->side[i]));
         LESASM_HIP_TRY(hipStreamWaitEvent(s, m->ev_join[i], 0));
     }
-    if (staged) launch_gather(m, kNumCat, rhs, s);
+    if (staged) launch_gather(m, m->n_gather >= kSplitGather ? kNumCat : 0, kNumCat + 1, rhs, s);
     LESASM_HIP_TRY(hipGetLastError());
     return LESASM_OK;
 }
