@@ -345,15 +345,16 @@ int lesasm_batch_get_per_type(const lesasm_batch *batch, int *per_type);
  * d_u[i] ([n_field_nodes_i][3]), d_p[i] (or d_p == NULL for none), nu[i],
  * d_rhs[i] (overwritten).  Same semantics as lesasm_assemble_momentum_rhs per
  * mesh (residual mode); all meshes use the first mesh's precision option.
- * Asynchronous: one small set-up kernel, the persistent element kernel and
- * one gather kernel.  A batch shares its members' staging rows: a call on
+ * Asynchronous: one small set-up kernel, the element kernel(s) and the
+ * gathers of shared nodes (in the per-type layouts, the nodes of one type
+ * only are gathered on that type's stream after its kernel).  A batch shares its members' staging rows: a call on
  * another stream than the previous call on the batch or on any member waits
  * for that call's end (as for lesasm_assemble_momentum_rhs). */
 int lesasm_batch_assemble(lesasm_batch *batch, const double *const *d_u, const double *const *d_p,
                           const double *nu, double *const *d_rhs, void *stream);
 
-/* Autotuner: times the batched assembly for chunk lengths {128, 256, 512,
- * 1024} x the three queue orders x {2, 4} workgroups per compute unit x the
+/* Autotuner: times the batched assembly for chunk lengths {each mesh's own
+ * per-type lengths, 128, 256, 512, 1024} x the three queue orders x {2, 4} workgroups per compute unit x the
  * three kernel layouts (the third without a grid size; median of `reps` runs
  * after one warm-up) and keeps the fastest.  With a cache_path, a line "signature chunk order grid per_type
  * ms" is looked up first

@@ -132,14 +132,16 @@ __device__ __forceinline__ int find_mesh(const int64_t *prefix, int n, int64_t i
     return lo;
 }
 
-// Shared nodes of every mesh: sum of staging rows (fixed order).
+// Shared nodes of every mesh: sum of staging rows (fixed order).  One class
+// of shared nodes at a time (the meshes' d_gnode ranges starting at gstart[i],
+// counted by gprefix), or all of them.
 __global__ void k_batch_gather(const BatchMeshDev *__restrict__ md, const BatchCall *__restrict__ call,
-                               const int64_t *__restrict__ gprefix, int nmesh) {
+                               const int64_t *__restrict__ gprefix, const int32_t *__restrict__ gstart, int nmesh) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= gprefix[nmesh]) return;
     const int mi = find_mesh(gprefix, nmesh, i);
     const BatchMeshDev &d = md[mi];
-    const int k = (int)(i - gprefix[mi]);
+    const int k = gstart[mi] + (int)(i - gprefix[mi]);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = d.goffs[k]; q < d.goffs[k + 1]; ++q) {
         const double *row = d.stage + 3 * (size_t)q;
@@ -195,7 +197,11 @@ struct lesasm_batch {
     BatchEntry *d_entries = nullptr;
     BatchCall *d_call = nullptr;
     BatchMeshDev *d_md = nullptr;
+    // shared-node classes (the meshes' gather_off): row c < kNumCat + 1 of
+    // d_gprefix / d_gstart is class c, row kNumCat + 1 every class at once
     int64_t *d_gprefix = nullptr, *d_nprefix = nullptr;
+    int32_t *d_gstart = nullptr;
+    int64_t class_gather[kNumCat + 2] = {0};
     int32_t *d_wentry = nullptr, *d_wchunk = nullptr;
     int *d_head = nullptr;
     int nwork = 0, lds_doubles = 0;
@@ -385,28 +391,47 @@ int build_work(lesasm_batch *b) {
 
 int build_tables(lesasm_batch *b) {
     const int n = (int)b->meshes.size();
+    constexpr int R = kNumCat + 2;  // rows: the classes, then all classes
     std::vector<BatchMeshDev> md(n);
-    std::vector<int64_t> gp(n + 1, 0), np(n + 1, 0);
+    std::vector<int64_t> gp((size_t)R * (n + 1), 0), np(n + 1, 0);
+    std::vector<int32_t> gs((size_t)R * n, 0);
     for (int i = 0; i < n; ++i) {
         lesasm_mesh *m = b->meshes[i];
         md[i] = BatchMeshDev{m->d_gnode, m->d_goffs, m->d_stage, m->d_mass};
-        gp[i + 1] = gp[i] + m->n_gather;
+        for (int c = 0; c < R; ++c) {
+            const int a = c <= kNumCat ? m->gather_off[c] : 0;
+            const int e = c <= kNumCat ? m->gather_off[c + 1] : m->n_gather;
+            gs[(size_t)c * n + i] = a;
+            gp[(size_t)c * (n + 1) + i + 1] = gp[(size_t)c * (n + 1) + i] + (e - a);
+        }
         np[i + 1] = np[i] + m->n_field;
     }
-    b->total_gather = gp[n];
+    for (int c = 0; c < R; ++c) b->class_gather[c] = gp[(size_t)c * (n + 1) + n];
+    b->total_gather = b->class_gather[kNumCat + 1];
     b->total_nodes = np[n];
     b->node_off = np;
     bfree(b, b->d_md);
     bfree(b, b->d_gprefix);
+    bfree(b, b->d_gstart);
     bfree(b, b->d_nprefix);
     int st;
-    if ((st = balloc(b, &b->d_md, (size_t)n)) || (st = balloc(b, &b->d_gprefix, (size_t)n + 1)) ||
-        (st = balloc(b, &b->d_nprefix, (size_t)n + 1)))
+    if ((st = balloc(b, &b->d_md, (size_t)n)) || (st = balloc(b, &b->d_gprefix, gp.size())) ||
+        (st = balloc(b, &b->d_gstart, gs.size())) || (st = balloc(b, &b->d_nprefix, (size_t)n + 1)))
         return st;
     LESASM_HIP_TRY(hipMemcpy(b->d_md, md.data(), sizeof(BatchMeshDev) * n, hipMemcpyHostToDevice));
-    LESASM_HIP_TRY(hipMemcpy(b->d_gprefix, gp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    LESASM_HIP_TRY(hipMemcpy(b->d_gprefix, gp.data(), sizeof(int64_t) * gp.size(), hipMemcpyHostToDevice));
+    LESASM_HIP_TRY(hipMemcpy(b->d_gstart, gs.data(), sizeof(int32_t) * gs.size(), hipMemcpyHostToDevice));
     LESASM_HIP_TRY(hipMemcpy(b->d_nprefix, np.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
     return LESASM_OK;
+}
+
+// Gather of shared-node class c (kNumCat + 1: every class) of every mesh on s.
+void launch_batch_gather(lesasm_batch *b, int c, hipStream_t s) {
+    const int64_t n = b->class_gather[c];
+    if (n <= 0) return;
+    const int nm = (int)b->meshes.size();
+    hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b->d_md, b->d_call,
+                       b->d_gprefix + (size_t)c * (nm + 1), b->d_gstart + (size_t)c * nm, nm);
 }
 
 int rebuild(lesasm_batch *b) {
@@ -481,11 +506,14 @@ int batch_launch(lesasm_batch *b, const BatchCall &call, bool has_p, bool fp32, 
             case LESASM_PEN06: launch_type<LESASM_PEN06>(b, k, has_p, fp32, sk); break;
             case LESASM_HEX08: launch_type<LESASM_HEX08>(b, k, has_p, fp32, sk); break;
             }
+            // the shared nodes of this type only, behind its kernel on its stream
+            launch_batch_gather(b, k, sk);
         }
         for (int i = 0; i + 1 < used; ++i) {
             LESASM_HIP_TRY(hipEventRecord(b->ev_join[i], b->side[i]));
             LESASM_HIP_TRY(hipStreamWaitEvent(s, b->ev_join[i], 0));
         }
+        launch_batch_gather(b, kNumCat, s);  // nodes of several types, or of none
     } else if (b->nwork > 0) {
         if (fp32) {
             if (has_p) hipLaunchKernelGGL((k_batch_assemble<float, true>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
@@ -495,9 +523,7 @@ int batch_launch(lesasm_batch *b, const BatchCall &call, bool has_p, bool fp32, 
             else hipLaunchKernelGGL((k_batch_assemble<double, false>), dim3(grid), dim3(256), shm, s, b->d_entries, b->d_call, b->d_wentry, b->d_wchunk, b->nwork, b->d_head);
         }
     }
-    if (b->total_gather > 0)
-        hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((b->total_gather + 255) / 256)), dim3(256), 0, s, b->d_md,
-                           b->d_call, b->d_gprefix, (int)b->meshes.size());
+    if (!(b->per_type && b->nwork > 0)) launch_batch_gather(b, kNumCat + 1, s);
     LESASM_HIP_TRY(hipGetLastError());
     return LESASM_OK;
 }
@@ -653,7 +679,7 @@ extern "C" int lesasm_batch_tune(lesasm_batch *b, const double *const *d_u, cons
     int st = make_call(b, d_u, d_p, nu, d_rhs, call);
     if (st) return st;
     const bool fp32 = b->meshes[0]->precision == LESASM_PREC_FP32;
-    const int chunks[] = {128, 256, 512, 1024};
+    const int chunks[] = {0, 128, 256, 512, 1024};  // 0: each mesh's own lengths per type
     const int orders[] = {LESASM_ORDER_MESH, LESASM_ORDER_LARGEST_FIRST, LESASM_ORDER_INTERLEAVED};
     const int grids[] = {2, 4};
     double best = 1e30;
