@@ -206,6 +206,16 @@ def host_cpu() -> dict:
             "logical_cpus": os.cpu_count(), "cpus_allowed": len(os.sched_getaffinity(0))}
 
 
+def child_processes() -> list:
+    """Processes this one started that are still alive (the benchmark starts
+    none: the oracle's timing leg runs as OpenMP threads in this process)."""
+    try:
+        import psutil
+    except ImportError:
+        return []
+    return [{"pid": c.pid, "name": c.name()} for c in psutil.Process().children(recursive=True)]
+
+
 def baseline_threads() -> int:
     """Threads for the all-core oracle leg: OMP_NUM_THREADS if set (the CPU
     share of this process), else every CPU it may run on."""
@@ -486,6 +496,7 @@ def run_main(args):
         print(f"  hybrid2m sub-record ({time.time() - t1:.0f} s)", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, t_oracle)
+    out["child_processes_at_end"] = child_processes()
     print(json.dumps(out), flush=True)
 
 
