@@ -36,6 +36,7 @@ def field_errors(got, ref):
 
 
 def assert_close(got, ref, tol, what=""):
+    assert np.isfinite(got).all(), (what, "non-finite output: a node left unwritten or a NaN")
     errs = field_errors(got, ref)
     worst = max(max(e) for e in errs)
     print(f"  {what}: worst per-field error {worst:.3e}", flush=True)
@@ -52,7 +53,8 @@ def run_gpu(torch, case, colour=False, keep_order=False, precision="fp64", with_
     m.precision = precision
     u = m.to_internal(torch.from_numpy(case.u).cuda())
     p = m.to_internal(torch.from_numpy(case.p).cuda()) if (with_p and case.p is not None) else None
-    rhs = m.to_user(m.assemble_momentum_rhs(u, p, case.nu))
+    # NaN-filled output: every scatter mode must write every node
+    rhs = m.to_user(m.assemble_momentum_rhs(u, p, case.nu, out=torch.full_like(u, float("nan"))))
     torch.cuda.synchronize()
     return rhs.cpu().numpy(), m
 
