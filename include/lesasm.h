@@ -153,11 +153,14 @@ int lesasm_mesh_filter_width(const lesasm_mesh *mesh, double *d_out, void *strea
 #define LESASM_OPT_PRECISION 1    /* LESASM_PREC_FP64 (default) or LESASM_PREC_FP32 */
 #define LESASM_OPT_RHS_MODE 2     /* LESASM_RHS_RESIDUAL (default) or LESASM_RHS_INCREMENT */
 #define LESASM_OPT_CHECK_FINITE 3 /* 1: scan u and p for NaN/Inf first (synchronises) */
-#define LESASM_OPT_BLOCK 4        /* threads per block of the assembly kernels: 64, 128 or 256 */
+#define LESASM_OPT_BLOCK 4        /* threads per block of the assembly kernels: 64, 128 or 256
+                                     (default); with 256, FP32 contractions of chunks longer than
+                                     512 elements run in blocks of 512 */
 #define LESASM_OPT_PROFILE 5      /* 1: record HIP events around every kernel launch */
 #define LESASM_OPT_CHUNK 6        /* elements per chunk of the chunked scatters, 32..4096, or 0
                                      (default) for min(512, max(64, 2^floor(log2(n_type/256)))) per
-                                     type, 1024 for TET04 when that leaves at least 4096 chunks;
+                                     type, 1024 for TET04 and PEN06 when that leaves at least 4096
+                                     chunks;
                                      setting it rebuilds the chunks (synchronises) */
 #define LESASM_OPT_CONCURRENT 7   /* 1 (default): the element-type kernels of one chunked assembly run
                                      concurrently on forked streams (joined before return); 0: one

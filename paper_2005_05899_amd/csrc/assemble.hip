@@ -42,9 +42,10 @@ __global__ __launch_bounds__(256) void k_assemble(CatView c, const double *__res
 
 // Chunked scatters (see chunk_body).  Workgroup w processes chunks w, w + G,
 // w + 2G, ... of the G workgroups launched: one chunk each by default
-// (G = number of chunks), several with a smaller grid.
+// (G = number of chunks), several with a smaller grid.  The FP32 kernels also
+// run in workgroups of 512 threads (see dispatch_chunks).
 template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
-__global__ __launch_bounds__(256) void k_assemble_chunk(ChunkView c, int n_chunks, const double *__restrict__ xyz,
+__global__ __launch_bounds__(sizeof(R) == 4 ? 512 : 256) void k_assemble_chunk(ChunkView c, int n_chunks, const double *__restrict__ xyz,
                                                         const double *__restrict__ u,
                                                         const double *__restrict__ p, double nu, double cv,
                                                         double *__restrict__ rhs) {
@@ -181,6 +182,15 @@ static void dispatch_chunks(const Category &c, double *stage, const ClosureView 
     ChunkView v{c.d_eoff, c.d_goff, c.d_gnodes, c.d_foff, c.d_fnodes, c.d_fslot, c.d_lg, c.d_lf, c.d_delta, stage,
                 (int32_t)c.n};
     const size_t shm = sizeof(double) * (size_t)c.lds_doubles;
+    // Chunks longer than 512 elements hold up to 64 KB of node data, so a
+    // compute unit keeps two of them: workgroups of 256 threads then cap the
+    // FP32 kernels below the wavefronts their registers allow.  Those run in
+    // workgroups of 512 threads (20 M hybrid box, FP32: PEN06 373 against 554
+    // us, TET04 146 against 164).  Measured and not taken: 384 threads for the
+    // FP32 HEX08 kernel (chunks of 512, three wavefronts per SIMD by its
+    // registers), 551 against 352 us; 512 threads for the FP64 TET04 kernel,
+    // 192 against 184 us.
+    if (sizeof(R) == 4 && !cl && block == 256 && c.chunk_elems > 512) block = 512;
     switch (c.type) {
     case LESASM_TET04: launch_chunks<LESASM_TET04, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, persist, s, xyz, u, p, nu, cv, rhs); break;
     case LESASM_PYR05: launch_chunks<LESASM_PYR05, R, STAGED>(v, c.n_chunks, shm, cl, has_p, periodic, block, persist, s, xyz, u, p, nu, cv, rhs); break;

@@ -267,9 +267,10 @@ static int chunk_length(const lesasm_mesh *m, int type, int64_t n) {
     if (m->chunk_elems) return m->chunk_elems;
     int ce = 64;
     while (ce < 512 && 2 * ce <= n / 256) ce *= 2;
-    // TET04's light elements gain from longer chunks (fewer shared nodes per
-    // element) once the category still fills the GPU many times over
-    if (type == LESASM_TET04 && ce == 512 && n / 1024 >= 4096) ce = 1024;
+    // TET04 and PEN06 gain from longer chunks (fewer shared nodes per element,
+    // so fewer staging rows) once the category still makes at least 4096 of
+    // them; HEX08 and PYR05 do not (HEX08 measured slower at 1024)
+    if ((type == LESASM_TET04 || type == LESASM_PEN06) && ce == 512 && n / 1024 >= 4096) ce = 1024;
     return ce;
 }
 
