@@ -56,9 +56,10 @@ __global__ __launch_bounds__(sizeof(R) == 4 ? 512 : 256) void k_assemble_chunk(C
     }
 }
 
-// The same with the learned closure (network weights after the node data in LDS).
+// The same with the learned closure (network weights after the node data in
+// LDS), with a register budget of two wavefronts per SIMD (see mlp_passes).
 template <int T, typename R, bool HAS_P, bool PERIODIC, bool STAGED>
-__global__ __launch_bounds__(256) void k_assemble_chunk_mlp(ChunkView c, const double *__restrict__ xyz,
+__global__ __launch_bounds__(256, 2) void k_assemble_chunk_mlp(ChunkView c, const double *__restrict__ xyz,
                                                             const double *__restrict__ u,
                                                             const double *__restrict__ p, double nu, double cv,
                                                             double *__restrict__ rhs, ClosureView cl,

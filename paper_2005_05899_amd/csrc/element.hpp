@@ -172,15 +172,29 @@ struct MlpCtx {
     float logd;  // log(Delta_e / Delta_ref)
 };
 
+// Passes of the network per round of 64 Gauss points (mlp_wave), chosen per
+// kernel by measurement on the 20 M hybrid box.  FP32: two for TET04 and PYR05
+// (162 -> 130 and 200 -> 166 registers, three wavefronts per SIMD), one for
+// PEN06 and HEX08 (which stay at two wavefronts either way; one pass reads the
+// weight tiles once).  FP64: together with a two-wavefront register budget on
+// the kernel (which spills 68 bytes per lane for PEN06 and 260 for HEX08),
+// two for TET04 and PEN06, four for PYR05 and HEX08: the FP64 closure assembly
+// 4.08 against 4.63 ms with one pass (PEN06 and HEX08 then at one wavefront).
+template <int T, typename R>
+constexpr int mlp_passes() {
+    if constexpr (sizeof(R) == 4) return (T == LESASM_TET04 || T == LESASM_PYR05) ? 2 : 1;
+    else return (T == LESASM_TET04 || T == LESASM_PEN06) ? 2 : 4;
+}
+
 // Subgrid stress of the network minus Vreman's (-nu_t S, S = G + G^T), as the
 // stress-flux tile T'_ik = w sum_j dtau_ij adj_kj of one Gauss point.
-template <typename R>
+template <typename R, int PASSES>
 __device__ __forceinline__ void mlp_stress_flux(const MlpCtx &mc, const R (&G)[3][3], const R (&S)[3][3], R nut,
                                                 R d2, R adj[3][3], R w, R (&Tp)[3][3]) {
     float x[kMlpIn], y[kMlpOut];
     R gn2;
     mlp_features<R>(G, mc.logd, x, gn2);
-    mlp_wave(mc.w, x, y, mc.scratch);
+    mlp_wave<PASSES>(mc.w, x, y, mc.scratch);
     const float tr = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
     const R sc = d2 * gn2;
     R dt[3][3];
@@ -269,7 +283,7 @@ __device__ __forceinline__ void tet_residual(const ElementData<LESASM_TET04, R> 
     }
     if constexpr (MLP) {  // constant gradient: one network evaluation per element
         R Tp[3][3];
-        mlp_stress_flux<R>(*mc, G, S, nut, d2, adj, (R)(1.0 / 6.0), Tp);
+        mlp_stress_flux<R, mlp_passes<LESASM_TET04, R>()>(*mc, G, S, nut, d2, adj, (R)(1.0 / 6.0), Tp);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             dacc[0][i] = -(Tp[i][0] + Tp[i][1] + Tp[i][2]);
@@ -399,7 +413,7 @@ __device__ __forceinline__ void element_residual(const ElementData<T, R> &d, R n
             for (int i = 0; i < 3; ++i) M::template test<true>(F[i], q, o.f[i], o.T[i]);
             if constexpr (MLP) {
                 R Tp[3][3];
-                mlp_stress_flux<R>(*mc, o.G, o.S, o.nut, d2, o.adj, -w, Tp);
+                mlp_stress_flux<R, mlp_passes<T, R>()>(*mc, o.G, o.S, o.nut, d2, o.adj, -w, Tp);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) M::template test<false>(dF[i], q, (R)0, Tp[i]);
             }

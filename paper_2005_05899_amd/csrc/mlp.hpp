@@ -37,8 +37,10 @@ constexpr int kMlpW2Shorts = 4 * 64 * 4;   // offset of the W2 tiles
 constexpr int kMlpW3Tile = 20;              // first W3 tile, in 64 x 4 units
 // LDS bytes of the packed weights and biases (b1, b2, b3 padded to 8)
 constexpr int kMlpLdsBytes = kMlpPackedShorts * 2 + (kMlpH + kMlpH + 8) * 4;
-// per-wavefront LDS scratch: 64 samples x 16 bf16 inputs, then 64 x 8 floats outputs
-constexpr int kMlpWaveScratch = 64 * 16 * 2 + 64 * 8 * 4;
+// per-wavefront LDS scratch: 64 samples x 16 bf16 inputs (32 bytes per sample),
+// over which the 64 x 8 float outputs (32 bytes per sample) are written once
+// the sample's inputs have been read
+constexpr int kMlpWaveScratch = 64 * 16 * 2;
 
 // Round-to-nearest-even float -> bf16 bits (finite inputs).
 __device__ __forceinline__ short f2bf(float f) {
@@ -106,13 +108,19 @@ __device__ __forceinline__ bf16x8_t cat_bf16x8(bf16x4_t lo, bf16x4_t hi) {
 // (matrix instructions ignore the execution mask).  scratch: kMlpWaveScratch
 // bytes of LDS private to this wavefront.  Biases enter as the accumulator
 // input of the first matrix instruction of each tile; layer 2 and layer 3 run
-// row tile by row tile, so only one row tile of H2 is ever held.
+// row tile by row tile, so only one row tile of H2 is ever held.  PASSES = 2
+// or 4 runs the chain on 32 or 16 samples at a time (a half or a quarter of
+// the live activations, the weight tiles read as many times), for kernels
+// whose occupancy that raises.
+template <int PASSES = 1>
 __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpIn], float (&y)[kMlpOut],
                                          unsigned char *scratch) {
+    static_assert(PASSES == 1 || PASSES == 2 || PASSES == 4, "one, two or four passes");
+    constexpr int NT = 4 / PASSES;  // sample tiles of 16 per pass
     const int lane = __lane_id();
     const int lq = lane >> 4, lr = lane & 15;
-    short *xs = (short *)scratch;                 // [64][16]
-    float *ys = (float *)(scratch + 64 * 16 * 2);  // [64][8]
+    short *xs = (short *)scratch;  // [64][16] inputs
+    float *ys = (float *)scratch;  // [64][8] outputs, sample j over input row j
     {
         const bf16x4_t v0 = pack_bf16x4(x[0], x[1], x[2], x[3]);
         const bf16x4_t v1 = pack_bf16x4(x[4], x[5], x[6], x[7]);
@@ -126,57 +134,61 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    // B operands of layer 1: X^T[k][sample], sample = 16 nt + lr, k = 4 lq + t
-    bf16x4_t bx[4];
+#pragma unroll 1
+    for (int pass = 0; pass < PASSES; ++pass) {  // not unrolled: the passes must not overlap
+        // B operands of layer 1: X^T[k][sample], sample = 16 nt + lr, k = 4 lq + t
+        bf16x4_t bx[NT];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) bx[nt] = ((const bf16x4_t *)(xs + 16 * (16 * nt + lr)))[lq];
+        for (int t = 0; t < NT; ++t) bx[t] = ((const bf16x4_t *)(xs + 16 * (16 * (NT * pass + t) + lr)))[lq];
 
-    // layer 1: H1^T = relu(W1^T X^T + b1), 4 row tiles x 4 sample tiles
-    bf16x4_t h1[4][4];  // [k-step = row tile][sample tile]
+        // layer 1: H1^T = relu(W1^T X^T + b1), 4 row tiles x NT sample tiles
+        bf16x4_t h1[4][NT];  // [k-step = row tile][sample tile]
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const bf16x4_t a = w.tiles[mt * 64 + lane];
-        const f32x4_t b = *(const f32x4_t *)(w.b1 + 16 * mt + 4 * lq);
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x4_t a = w.tiles[mt * 64 + lane];
+            const f32x4_t b = *(const f32x4_t *)(w.b1 + 16 * mt + 4 * lq);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bx[nt], b, 0, 0, 0);
-            h1[mt][nt] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
+            for (int t = 0; t < NT; ++t) {
+                const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bx[t], b, 0, 0, 0);
+                h1[mt][t] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
+            }
         }
-    }
-    // layers 2 and 3 by row tile of H2: H2^T = relu(W2^T H1^T + b2), Y^T += W3^T H2^T
-    f32x4_t acc3[4];
-    {
-        const f32x4_t b3 = lq < 2 ? *(const f32x4_t *)(w.b3 + 4 * lq) : f32x4_t{0.f, 0.f, 0.f, 0.f};
+        // layers 2 and 3 by row tile of H2: H2^T = relu(W2^T H1^T + b2), Y^T += W3^T H2^T
+        f32x4_t acc3[NT];
+        {
+            const f32x4_t b3 = lq < 2 ? *(const f32x4_t *)(w.b3 + 4 * lq) : f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc3[nt] = b3;
-    }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const f32x4_t b = *(const f32x4_t *)(w.b2 + 16 * mt + 4 * lq);
-        f32x4_t acc[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = b;
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8_t a = w.w2[(2 * mt + kb) * 64 + lane];
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, cat_bf16x8(h1[2 * kb][nt], h1[2 * kb + 1][nt]),
-                                                                  acc[nt], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) acc3[t] = b3;
         }
-        const bf16x4_t a3 = w.tiles[(kMlpW3Tile + mt) * 64 + lane];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const bf16x4_t h2 = relu_bf16x4(pack_bf16x4(acc[nt][0], acc[nt][1], acc[nt][2], acc[nt][3]));
-            acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, h2, acc3[nt], 0, 0, 0);
+        for (int mt = 0; mt < 4; ++mt) {
+            const f32x4_t b = *(const f32x4_t *)(w.b2 + 16 * mt + 4 * lq);
+            f32x4_t acc[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = b;
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8_t a = w.w2[(2 * mt + kb) * 64 + lane];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, cat_bf16x8(h1[2 * kb][t], h1[2 * kb + 1][t]),
+                                                                     acc[t], 0, 0, 0);
+            }
+            const bf16x4_t a3 = w.tiles[(kMlpW3Tile + mt) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x4_t h2 = relu_bf16x4(pack_bf16x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
+                acc3[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, h2, acc3[t], 0, 0, 0);
+            }
         }
+        // Y^T rows 0..5 (lanes with lq < 2 hold rows 0..7), over the input rows
+        // of this pass's samples, which no later pass reads
+        if (lq < 2)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ys[8 * (16 * (NT * pass + t) + lr) + 4 * lq + q] = acc3[t][q];
     }
-    // Y^T rows 0..5 (lanes with lq < 2 hold rows 0..7)
-    if (lq < 2)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) ys[8 * (16 * nt + lr) + 4 * lq + t] = acc3[nt][t];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
