@@ -92,31 +92,36 @@ def test_small_hybrid_fp64(torch_cuda, small, scatter, keep):
     m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("scatter", ["staged", "chunk_atomic"])
-@pytest.mark.parametrize("chunk", [32, 100, 4096, 0])
-def test_chunk_sizes(torch_cuda, small, periodic, chunk, scatter):
-    """Many small chunks (ragged last chunks), one chunk per type, and the
-    per-type default; the periodic cube exercises separate geometry and field
-    node lists."""
+@pytest.mark.parametrize("chunk", [32, 100, 1024, 4096, 0])
+def test_chunk_sizes(torch_cuda, small, periodic, chunk, scatter, precision):
+    """Many small chunks (ragged last chunks), chunks longer than a workgroup
+    (FP32: 512-thread workgroups, several elements per thread), one chunk per
+    type, and the per-type default; the periodic cube exercises separate
+    geometry and field node lists."""
+    tol = TOL64 if precision == "fp64" else TOL32
     for c, ref in (small, periodic):
-        got, m = run_gpu(torch_cuda, c, chunk=chunk, scatter=scatter)
-        assert_close(got, ref, TOL64, f"{c.name} {scatter} chunk={chunk}")
+        got, m = run_gpu(torch_cuda, c, chunk=chunk, scatter=scatter, precision=precision)
+        assert_close(got, ref, tol, f"{c.name} {scatter} chunk={chunk} {precision}")
         m.close()
 
 
+@pytest.mark.parametrize("chunk", [32, 1024])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("persist", [0, 1, 3])
-def test_persistent_chunk_loop(torch_cuda, small, periodic, persist, precision):
+def test_persistent_chunk_loop(torch_cuda, small, periodic, persist, precision, chunk):
     """Workgroups looping over chunks: one workgroup per chunk (0), as many as
     the GPU holds (1), and three workgroups that each process many chunks (3),
-    with short chunks so that every workgroup loops."""
+    with short chunks so that every workgroup loops, and with chunks longer
+    than a workgroup (FP32 in 512-thread workgroups)."""
     from paper_2005_05899_amd import lesasm
     tol = TOL64 if precision == "fp64" else TOL32
     for c, ref in (small, periodic):
         m = lesasm.Mesh.from_arrays(c.mesh, c.vreman_c)
         m.set_option(lesasm.OPT_PERSISTENT, persist)
-        got, m = run_gpu(torch_cuda, c, chunk=32, mesh=m, precision=precision)
-        assert_close(got, ref, tol, f"{c.name} persist={persist} {precision}")
+        got, m = run_gpu(torch_cuda, c, chunk=chunk, mesh=m, precision=precision)
+        assert_close(got, ref, tol, f"{c.name} persist={persist} chunk={chunk} {precision}")
         m.close()
 
 
