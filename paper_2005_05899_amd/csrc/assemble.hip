@@ -75,8 +75,16 @@ __global__ void k_gather_shared(const int32_t *__restrict__ gnode, const int32_t
                                 const double *__restrict__ stage, double *__restrict__ rhs, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int q = goffs[i]; q < goffs[i + 1]; ++q) {
+    // A shared node has two rows or more (a node of no element none): the
+    // first two are loaded together, before the loop over the rest; the sum
+    // still runs in row order.
+    const int q0 = goffs[i], q1 = goffs[i + 1];
+    const double *r = stage + 3 * (size_t)q0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    if (q1 > q0) a0 = r[0], a1 = r[1], a2 = r[2];
+    if (q1 > q0 + 1) b0 = r[3], b1 = r[4], b2 = r[5];
+    double s0 = a0 + b0, s1 = a1 + b1, s2 = a2 + b2;
+    for (int q = q0 + 2; q < q1; ++q) {
         const double *row = stage + 3 * (size_t)q;
         s0 += row[0];
         s1 += row[1];

@@ -142,8 +142,14 @@ __global__ void k_batch_gather(const BatchMeshDev *__restrict__ md, const BatchC
     const int mi = find_mesh(gprefix, nmesh, i);
     const BatchMeshDev &d = md[mi];
     const int k = gstart[mi] + (int)(i - gprefix[mi]);
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int q = d.goffs[k]; q < d.goffs[k + 1]; ++q) {
+    // as k_gather_shared: the first two rows loaded together, summed in row order
+    const int q0 = d.goffs[k], q1 = d.goffs[k + 1];
+    const double *r = d.stage + 3 * (size_t)q0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    if (q1 > q0) a0 = r[0], a1 = r[1], a2 = r[2];
+    if (q1 > q0 + 1) b0 = r[3], b1 = r[4], b2 = r[5];
+    double s0 = a0 + b0, s1 = a1 + b1, s2 = a2 + b2;
+    for (int q = q0 + 2; q < q1; ++q) {
         const double *row = d.stage + 3 * (size_t)q;
         s0 += row[0];
         s1 += row[1];
