@@ -122,26 +122,24 @@ __global__ __launch_bounds__(256) void k_batch_assemble_type(const BatchEntry *_
     }
 }
 
-__device__ __forceinline__ int find_mesh(const int64_t *prefix, int n, int64_t i) {
-    int lo = 0, hi = n;  // largest m with prefix[m] <= i
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
+// A block of at most 256 consecutive nodes of one mesh: the gather and update
+// kernels give each workgroup one, so that the mesh index, and every pointer
+// read through it, is uniform over the workgroup (scalar loads, no search).
+struct BatchBlock {
+    int32_t mesh, first, end;  // node range [first, end) of the mesh's list
+};
+constexpr int kBatchBlock = 256;
 
 // Shared nodes of every mesh: sum of staging rows (fixed order).  One class
-// of shared nodes at a time (the meshes' d_gnode ranges starting at gstart[i],
-// counted by gprefix), or all of them.
-__global__ void k_batch_gather(const BatchMeshDev *__restrict__ md, const BatchCall *__restrict__ call,
-                               const int64_t *__restrict__ gprefix, const int32_t *__restrict__ gstart, int nmesh) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= gprefix[nmesh]) return;
-    const int mi = find_mesh(gprefix, nmesh, i);
-    const BatchMeshDev &d = md[mi];
-    const int k = gstart[mi] + (int)(i - gprefix[mi]);
+// of shared nodes at a time (blocks over the meshes' d_gnode ranges of that
+// class), or all of them.
+__global__ __launch_bounds__(kBatchBlock) void k_batch_gather(const BatchMeshDev *__restrict__ md,
+                                                               const BatchCall *__restrict__ call,
+                                                               const BatchBlock *__restrict__ blk) {
+    const BatchBlock bk = blk[blockIdx.x];
+    const int k = bk.first + (int)threadIdx.x;
+    if (k >= bk.end) return;
+    const BatchMeshDev d = md[bk.mesh];
     // as k_gather_shared: the first two rows loaded together, summed in row order
     const int q0 = d.goffs[k], q1 = d.goffs[k + 1];
     const double *r = d.stage + 3 * (size_t)q0;
@@ -155,13 +153,13 @@ __global__ void k_batch_gather(const BatchMeshDev *__restrict__ md, const BatchC
         s1 += row[1];
         s2 += row[2];
     }
-    double *dst = call->rhs[mi] + 3 * (size_t)d.gnode[k];
+    double *dst = call->rhs[bk.mesh] + 3 * (size_t)d.gnode[k];
     dst[0] = s0;
     dst[1] = s1;
     dst[2] = s2;
 }
 
-// Runge-Kutta update over all meshes' nodes (node ranges by prefix):
+// Runge-Kutta update over all meshes' nodes (blocks of one mesh each):
 //   kout = dt M^-1 rhs (in place in rhs), then y = base + a1 k1 + a2 kout.
 struct UpdateArgs {
     const double *base[kMaxBatch];
@@ -171,20 +169,22 @@ struct UpdateArgs {
     double a1, a2, dt;
 };
 
-__global__ void k_batch_update(UpdateArgs a, const BatchMeshDev *__restrict__ md, const int64_t *__restrict__ nprefix,
-                               int nmesh) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nprefix[nmesh]) return;
-    const int mi = find_mesh(nprefix, nmesh, i);
-    const size_t k = (size_t)(i - nprefix[mi]);
+__global__ __launch_bounds__(kBatchBlock) void k_batch_update(UpdateArgs a, const BatchMeshDev *__restrict__ md,
+                                                               const BatchBlock *__restrict__ blk) {
+    const BatchBlock bk = blk[blockIdx.x];
+    const int mi = bk.mesh;
+    const size_t k = (size_t)bk.first + threadIdx.x;
+    if (k >= (size_t)bk.end) return;
     const double s = a.dt / md[mi].mass[k];
+    double *rhs = a.rhs[mi], *y = a.y[mi];
+    const double *base = a.base[mi], *k1 = a.k1[mi];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double kv = s * a.rhs[mi][3 * k + c];
-        a.rhs[mi][3 * k + c] = kv;
-        double v = a.base[mi][3 * k + c] + a.a2 * kv;
-        if (a.k1[mi]) v += a.a1 * a.k1[mi][3 * k + c];
-        a.y[mi][3 * k + c] = v;
+        const double kv = s * rhs[3 * k + c];
+        rhs[3 * k + c] = kv;
+        double v = base[3 * k + c] + a.a2 * kv;
+        if (k1) v += a.a1 * k1[3 * k + c];
+        y[3 * k + c] = v;
     }
 }
 
@@ -203,10 +203,12 @@ struct lesasm_batch {
     BatchEntry *d_entries = nullptr;
     BatchCall *d_call = nullptr;
     BatchMeshDev *d_md = nullptr;
-    // shared-node classes (the meshes' gather_off): row c < kNumCat + 1 of
-    // d_gprefix / d_gstart is class c, row kNumCat + 1 every class at once
-    int64_t *d_gprefix = nullptr, *d_nprefix = nullptr;
-    int32_t *d_gstart = nullptr;
+    // node blocks (BatchBlock): row c < kNumCat + 1 the shared-node class c of
+    // every mesh (the meshes' gather_off), row kNumCat + 1 every class at once,
+    // row kNumCat + 2 every field node (the Runge-Kutta update); row r holds
+    // blocks [blk_off[r], blk_off[r + 1]) of d_blk
+    BatchBlock *d_blk = nullptr;
+    int blk_off[kNumCat + 4] = {0};
     int64_t class_gather[kNumCat + 2] = {0};
     int32_t *d_wentry = nullptr, *d_wchunk = nullptr;
     int *d_head = nullptr;
@@ -397,47 +399,50 @@ int build_work(lesasm_batch *b) {
 
 int build_tables(lesasm_batch *b) {
     const int n = (int)b->meshes.size();
-    constexpr int R = kNumCat + 2;  // rows: the classes, then all classes
+    constexpr int R = kNumCat + 3;  // rows: the classes, all classes, all field nodes
     std::vector<BatchMeshDev> md(n);
-    std::vector<int64_t> gp((size_t)R * (n + 1), 0), np(n + 1, 0);
-    std::vector<int32_t> gs((size_t)R * n, 0);
+    std::vector<BatchBlock> blk;
+    std::vector<int64_t> np(n + 1, 0);
     for (int i = 0; i < n; ++i) {
         lesasm_mesh *m = b->meshes[i];
         md[i] = BatchMeshDev{m->d_gnode, m->d_goffs, m->d_stage, m->d_mass};
-        for (int c = 0; c < R; ++c) {
-            const int a = c <= kNumCat ? m->gather_off[c] : 0;
-            const int e = c <= kNumCat ? m->gather_off[c + 1] : m->n_gather;
-            gs[(size_t)c * n + i] = a;
-            gp[(size_t)c * (n + 1) + i + 1] = gp[(size_t)c * (n + 1) + i] + (e - a);
-        }
         np[i + 1] = np[i] + m->n_field;
     }
-    for (int c = 0; c < R; ++c) b->class_gather[c] = gp[(size_t)c * (n + 1) + n];
+    for (int c = 0; c < R; ++c) {
+        b->blk_off[c] = (int)blk.size();
+        int64_t count = 0;
+        for (int i = 0; i < n; ++i) {
+            const lesasm_mesh *m = b->meshes[i];
+            const int64_t a = c <= kNumCat ? m->gather_off[c] : 0;
+            const int64_t e = c <= kNumCat ? m->gather_off[c + 1] : c == kNumCat + 1 ? m->n_gather : m->n_field;
+            for (int64_t f = a; f < e; f += kBatchBlock)
+                blk.push_back(BatchBlock{i, (int32_t)f, (int32_t)std::min(e, f + kBatchBlock)});
+            count += e - a;
+        }
+        if (c < kNumCat + 2) b->class_gather[c] = count;
+        if (blk.size() > (size_t)INT32_MAX) return fail(LESASM_E_UNSUPPORTED, "batch: too many node blocks");
+    }
+    b->blk_off[R] = (int)blk.size();
     b->total_gather = b->class_gather[kNumCat + 1];
     b->total_nodes = np[n];
     b->node_off = np;
     bfree(b, b->d_md);
-    bfree(b, b->d_gprefix);
-    bfree(b, b->d_gstart);
-    bfree(b, b->d_nprefix);
+    bfree(b, b->d_blk);
     int st;
-    if ((st = balloc(b, &b->d_md, (size_t)n)) || (st = balloc(b, &b->d_gprefix, gp.size())) ||
-        (st = balloc(b, &b->d_gstart, gs.size())) || (st = balloc(b, &b->d_nprefix, (size_t)n + 1)))
+    if ((st = balloc(b, &b->d_md, (size_t)n)) || (st = balloc(b, &b->d_blk, std::max<size_t>(blk.size(), 1))))
         return st;
     LESASM_HIP_TRY(hipMemcpy(b->d_md, md.data(), sizeof(BatchMeshDev) * n, hipMemcpyHostToDevice));
-    LESASM_HIP_TRY(hipMemcpy(b->d_gprefix, gp.data(), sizeof(int64_t) * gp.size(), hipMemcpyHostToDevice));
-    LESASM_HIP_TRY(hipMemcpy(b->d_gstart, gs.data(), sizeof(int32_t) * gs.size(), hipMemcpyHostToDevice));
-    LESASM_HIP_TRY(hipMemcpy(b->d_nprefix, np.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    if (!blk.empty())
+        LESASM_HIP_TRY(hipMemcpy(b->d_blk, blk.data(), sizeof(BatchBlock) * blk.size(), hipMemcpyHostToDevice));
     return LESASM_OK;
 }
 
 // Gather of shared-node class c (kNumCat + 1: every class) of every mesh on s.
 void launch_batch_gather(lesasm_batch *b, int c, hipStream_t s) {
-    const int64_t n = b->class_gather[c];
-    if (n <= 0) return;
-    const int nm = (int)b->meshes.size();
-    hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b->d_md, b->d_call,
-                       b->d_gprefix + (size_t)c * (nm + 1), b->d_gstart + (size_t)c * nm, nm);
+    const int nb = b->blk_off[c + 1] - b->blk_off[c];
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)nb), dim3(kBatchBlock), 0, s, b->d_md, b->d_call,
+                       b->d_blk + b->blk_off[c]);
 }
 
 int rebuild(lesasm_batch *b) {
@@ -752,7 +757,7 @@ static int rk3_record(lesasm_batch *b, double *const *d_u, const double *const *
         u_c[i] = d_u[i];
         us_c[i] = us[i];
     }
-    const unsigned gridn = (unsigned)((b->total_nodes + 255) / 256);
+    const unsigned gridn = (unsigned)(b->blk_off[kNumCat + 3] - b->blk_off[kNumCat + 2]);
     auto stage = [&](const std::vector<const double *> &uin, const std::vector<double *> &rhs, double a1,
                      const std::vector<double *> *k1v, double a2, std::vector<double *> &y) -> int {
         BatchCall call;
@@ -770,7 +775,8 @@ static int rk3_record(lesasm_batch *b, double *const *d_u, const double *const *
         ua.a1 = a1;
         ua.a2 = a2;
         ua.dt = dt;
-        hipLaunchKernelGGL(k_batch_update, dim3(gridn), dim3(256), 0, s, ua, b->d_md, b->d_nprefix, n);
+        hipLaunchKernelGGL(k_batch_update, dim3(gridn), dim3(kBatchBlock), 0, s, ua, b->d_md,
+                           b->d_blk + b->blk_off[kNumCat + 2]);
         LESASM_HIP_TRY(hipGetLastError());
         return LESASM_OK;
     };
