@@ -95,6 +95,11 @@ PART_MUTANTS = {
                          "Ups = np.cumsum(T, axis=1) / T.sum(axis=1, keepdims=True)"),
     "regression_weights_reversed": ("wk = growth ** np.arange(K)", "wk = growth ** -np.arange(K)"),
     "regression_cut_off_by_one": ("nxt = (i - alpha) / beta", "nxt = (i - 1 - alpha) / beta"),
+    "degenerate_spread_threshold_dropped": ("if x.max() - x.min() > 1e-12 * P and sxx > 0:", "if sxx > 0:"),
+    "degenerate_spread_threshold_too_wide": ("if x.max() - x.min() > 1e-12 * P and sxx > 0:",
+                                             "if x.max() - x.min() > 1e-6 * P and sxx > 0:"),
+    "negative_slope_accepted": ("if beta > 0:", "if beta != 0:"),
+    "fallback_keeps_the_newest_point": ("nxt = i * x[-1] / y[-1] if y[-1] > 0 else x[-1]", "nxt = x[-1]"),
 }
 
 

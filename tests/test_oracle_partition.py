@@ -215,6 +215,65 @@ def test_regression_matches_numpy_least_squares():
         assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
 
 
+def _origin_line(lam, t):
+    """Splitting points of the fallback: each on the line through the origin
+    and its newest observation, Lambda_i = i Lambda_i^K / Upsilon_i^K (then
+    clamped non-decreasing into [0, P])."""
+    Pn = len(lam)
+    Lam, Ups = np.cumsum(lam), np.cumsum(t) / np.mean(t)
+    pts = [0.0] + [i * Lam[i - 1] / Ups[i - 1] for i in range(1, Pn)] + [float(Pn)]
+    for i in range(1, Pn):
+        pts[i] = min(max(pts[i], pts[i - 1]), Pn)
+    return np.diff(pts)
+
+
+def test_degenerate_fits_fall_back_to_the_origin_line():
+    """Reading A27: one observation, a spread of Lambda_i below 1e-12 P, or a
+    non-increasing fit use the line through the origin and the newest point."""
+    lam = np.array([0.8, 1.3, 0.9, 1.0])
+    t1 = np.array([1.0, 2.0, 1.2, 1.1])
+    t2 = np.array([1.1, 1.9, 1.3, 1.0])
+    want = _origin_line(lam, t2)
+    # one observation
+    assert np.allclose(P.balance_update([lam], [t2]), want, rtol=0, atol=1e-14)
+    # two observations with the same coefficients (no spread), and a spread of
+    # 1e-15 P, below the threshold
+    for eps in (0.0, 1e-15):
+        lam2 = lam + eps * np.array([1.0, -1.0, 1.0, -1.0])
+        got = P.balance_update([lam, lam2], [t1, t2])
+        assert np.allclose(got, _origin_line(lam2, t2), rtol=0, atol=1e-12)
+    # a spread above the threshold, but times that fall as the split grows:
+    # every fitted slope is negative, so the fallback again
+    lamb = np.array([1.0, 1.0, 1.0, 1.0])
+    lama = lamb + 0.1 * np.array([1.0, -1.0, 1.0, -1.0])
+    ta = np.array([1.0, 1.0, 1.0, 1.0])
+    tb = np.array([1.3, 0.7, 1.3, 0.7])  # Upsilon_1 rises while Lambda_1 falls
+    got = P.balance_update([lama, lamb], [ta, tb])
+    assert np.allclose(got, _origin_line(lamb, tb), rtol=0, atol=1e-12)
+
+
+def test_spread_above_the_threshold_uses_the_fit():
+    """A spread of 1e-9 (above 1e-12 P) at every splitting point: the fit,
+    which with two observations is the line through both points, not the
+    fallback (which lands 0.2 away on this load)."""
+    Pn = 4
+    R = lambda s: s + 0.3 * s ** 2  # noqa: E731  work density rising along the curve
+    lam0 = np.ones(Pn)
+    lam1 = lam0 + 1e-9 * np.array([1.0, 1.0, 1.0, -3.0])  # every Lambda_i moves
+    t0, t1 = _times(lam0, R), _times(lam1, R)
+    L0, L1 = np.cumsum(lam0), np.cumsum(lam1)
+    U0, U1 = np.cumsum(t0) / t0.mean(), np.cumsum(t1) / t1.mean()
+    want = [0.0]
+    for i in range(1, Pn):
+        slope = (U1[i - 1] - U0[i - 1]) / (L1[i - 1] - L0[i - 1])
+        want.append(L1[i - 1] + (i - U1[i - 1]) / slope)
+    want.append(float(Pn))
+    got = np.concatenate([[0.0], np.cumsum(P.balance_update([lam0, lam1], [t0, t1], growth=1.0))])
+    assert np.allclose(got, want, rtol=0, atol=1e-9)
+    fallback = np.concatenate([[0.0], np.cumsum(_origin_line(lam1, t1))])
+    assert np.abs(fallback - want).max() > 0.1
+
+
 def test_weighted_iteration_converges_on_a_smooth_load():
     Pn = 8
     R = lambda s: s + 0.15 * s ** 2 + 0.3 * np.sin(s)  # noqa: E731  increasing cost along the curve
