@@ -79,3 +79,24 @@ def test_cpu_baseline_uses_the_threads_it_reports(monkeypatch):
     assert abs(cb["single_thread"]["value"] - c.mesh.n_elems / 0.5) < 1e-9
     monkeypatch.delenv("OMP_NUM_THREADS")
     assert bench.baseline_threads() == len(os.sched_getaffinity(0))
+
+
+def test_kernel_table_rates_and_per_assembly_gather():
+    """Per-kernel figures from summed event times: average per launch, flop
+    rate from the nominal counts, and the gather summed per assembly (it runs
+    as one launch per class of shared nodes)."""
+    m = mg.uniform_hex_box((2, 1, 1), (2.0, 1.0, 1.0))  # two HEX08 elements
+
+    class FakeMesh:
+        n_per_type = {4: 0, 5: 0, 6: 0, 8: 2}
+
+    kt = {"tet04": (0.0, 0), "pyr05": (0.0, 0), "pen06": (0.0, 0), "hex08": (3.0, 3),  # 3 launches, 1 ms each
+          "gather": (1.5, 15), "fill": (0.0, 0)}                                        # 5 launches per assembly
+    tab = bench.kernel_table(FakeMesh(), m, kt, 78.6)
+    assert set(tab) == {"hex08", "gather"}
+    h = tab["hex08"]
+    assert h["avg_ms"] == 1.0 and h["launches"] == 3 and h["elements"] == 2
+    assert abs(h["algorithmic_tflops"] - 2 * 7200 / 1e-3 / 1e12) < 1e-18
+    assert abs(h["frac_of_peak"] - h["algorithmic_tflops"] / 78.6) < 1e-18
+    g = tab["gather"]
+    assert g["ms_per_assembly"] == 0.5 and g["launches_per_assembly"] == 5 and g["avg_ms_per_launch"] == 0.1
