@@ -135,7 +135,7 @@ __device__ __forceinline__ void mlp_wave(const MlpLds &w, const float (&x)[kMlpI
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll 1
-    for (int pass = 0; pass < PASSES; ++pass) {  // not unrolled: the passes must not overlap
+    for (int pass = 0; pass < PASSES; ++pass) {  // not unrolled: the passes reuse the same registers
         // B operands of layer 1: X^T[k][sample], sample = 16 nt + lr, k = 4 lq + t
         bf16x4_t bx[NT];
 #pragma unroll
