@@ -410,7 +410,10 @@ def measure_workload(torch, args, workload, case, variants: bool, oracle_errors:
     ab = algorithmic_bytes(m, True)
     step_s = elapsed / args.steps
     total_flops = sum(FLOPS_PER_ELEMENT[t] * mesh.n_per_type[t] for t in SLOT)
-    traffic = traffic_from_profiles(dominant, workload)
+    # counter summaries exist per precision for the staged scatter only (other
+    # scatters and precisions run other kernels)
+    traffic = None if args.scatter != "staged" else \
+        traffic_from_profiles(dominant, workload if args.precision == "fp64" else f"{workload}_{args.precision}")
     desc = WORKLOADS[workload][0]
     rec = {
         "value": E * args.steps / elapsed,
@@ -419,7 +422,7 @@ def measure_workload(torch, args, workload, case, variants: bool, oracle_errors:
                    "elements": E, "field_nodes": m.n_field_nodes,
                    "per_type": {SLOT[t]: mesh.n_per_type[t] for t in SLOT},
                    "nu": case.nu, "vreman_c": case.vreman_c, "seeds": case.meta},
-        "roofline": {"bound": "alu", "kernel": f"k_assemble_chunk<{dominant}> (isolated launches)",
+        "roofline": {"bound": "alu", "kernel": f"k_assemble_chunk<{dominant}, {args.precision}> (isolated launches)",
                      "achieved": dk["algorithmic_tflops"], "peak": peak, "unit": "TFLOP/s",
                      "frac": dk["algorithmic_tflops"] / peak,
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
