@@ -503,7 +503,7 @@ def hybrid_2m_case() -> Case:
 
 
 def hybrid_20m_case() -> Case:
-    """The 20 M-element precision workload (205 x 205 cells)."""
+    """The 20 M-element hybrid workload (205 x 205 cells), the benchmark's default."""
     return hybrid_case(20_000_000, seed_mesh=4, seed_u=5, seed_p=12, n_xy=205)
 
 
