@@ -311,8 +311,8 @@ def hybrid2m():
 
 
 def test_hybrid_2m_fp64_full(torch_cuda, hybrid2m):
-    """The benchmark workload (2.0 M hybrid elements) in the benchmark's launch
-    configuration, every node compared with the oracle."""
+    """The benchmark's 2.0 M sub-record workload (2.0 M hybrid elements) in the
+    benchmark's launch configuration, every node compared with the oracle."""
     c, ref = hybrid2m
     got, m = run_gpu(torch_cuda, c)
     assert_close(got, ref, TOL64, "2M hybrid fp64 staged scatter")
