@@ -259,7 +259,12 @@ template <class T> static void dfree(lesasm_mesh *m, T *&p) {
 // Chunks for the chunked scatter of category k: runs of consecutive internal
 // elements, at most m->chunk_elems long and with at most m->chunk_max_nodes
 // distinct geometry and field nodes (800, or 400 when the learned closure
-// also needs LDS), so that a chunk's node data fit in LDS.  Node
+// also needs LDS), so that a chunk's node data fit in LDS.  With the closure,
+// PEN06 and HEX08 take 700: their closure kernels hold two workgroups per
+// compute unit (registers), so 56 KB of node data beside the 21 KB of weights
+// and scratch still fit twice, while the TET04 and PYR05 closure kernels hold
+// three (20 M hybrid box: FP32 closure 2.71 against 2.79 ms, FP64 3.92 against
+// 4.09 ms).  Node
 // lists are sorted ascending (coalesced loads); a field node is owned by a
 // chunk when all of its incidences in the mesh lie in that chunk.
 
@@ -295,6 +300,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
     const int nnode = c.type;
     const int64_t n = c.n;
     const int ce = chunk_length(m, c.type, n);
+    const int cap = (m->mlp && (c.type == LESASM_PEN06 || c.type == LESASM_HEX08)) ? 700 : m->chunk_max_nodes;
     c.chunk_elems = ce;
     std::vector<int32_t> eoff{0}, goff{0}, foff{0}, gnodes, fnodes;
     std::vector<uint16_t> lg((size_t)nnode * n), lf(periodic ? (size_t)nnode * n : 0);
@@ -311,7 +317,7 @@ static int build_chunks(lesasm_mesh *m, int k) {
                 newg += gslot[cg[(size_t)a * n + e]] < 0;
                 newf += fslot[cf[(size_t)a * n + e]] < 0;
             }
-            if (e > start && ((int)gl.size() + newg > m->chunk_max_nodes || (int)fl.size() + newf > m->chunk_max_nodes))
+            if (e > start && ((int)gl.size() + newg > cap || (int)fl.size() + newf > cap))
                 break;
             for (int a = 0; a < nnode; ++a) {
                 const int32_t g = cg[(size_t)a * n + e], f = cf[(size_t)a * n + e];
